@@ -1,0 +1,194 @@
+"""FP64 CPU oracle of the sparse D3Q19 LBGK update -- TEST INFRASTRUCTURE ONLY.
+
+Only the test suite, the smoke check and the benchmark's CPU-baseline leg may
+import this package.  It shares no code with the GPU library; the only thing
+both consume is the geometry produced by the seeded input generators.
+
+Thin ctypes marshalling over ``oracle.c`` (plain C, FP64, array-of-structures,
+push order, input site order).  Geometry objects are duck-typed: anything with
+``coords`` (n,3) int32, ``nbr`` (n,19) int32 and ``iolets`` (objects with
+kind, role, centre, normal, radius, vdir, table).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "liboracle.so")
+_lib = None
+Q = 19
+
+
+def build(verbose: bool = False) -> str:
+    """Compile liboracle.so (gcc, -O2, no FP contraction, OpenMP)."""
+    srcs = [os.path.join(_HERE, s) for s in ("oracle.c", "oracle_adjoint.c") if os.path.exists(os.path.join(_HERE, s))]
+    cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC", "-shared",
+           *srcs, "-o", _SO, "-lm"]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.check_call(cmd)
+    return _SO
+
+
+class _Iolet(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("role", ctypes.c_int32), ("centre", ctypes.c_double * 3),
+                ("normal", ctypes.c_double * 3), ("radius", ctypes.c_double), ("vdir", ctypes.c_double * 3),
+                ("table", ctypes.c_void_p), ("table_len", ctypes.c_int64)]
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_SO):
+        build()
+    lib = ctypes.CDLL(_SO)
+    P, i64, i32, d = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
+    lib.orc_lattice.argtypes = [P, P, P]
+    lib.orc_equilibrium.argtypes = [d, P, P]
+    lib.orc_moments.argtypes = [P, P, P]
+    lib.orc_collide.argtypes = [P, d, P]
+    lib.orc_init.argtypes = [i64, P, P, d, P]
+    lib.orc_step.argtypes = [i64, P, P, d, d, P, i32, P, i64, P, P, P, P]
+    lib.orc_step.restype = ctypes.c_int
+    lib.orc_run.argtypes = [i64, P, P, d, d, P, i32, P, i64, i64, P, P, P]
+    lib.orc_run.restype = ctypes.c_int
+    lib.orc_macros.argtypes = [i64, P, d, P, P, P, P]
+    lib.orc_mass.argtypes = [i64, P]
+    lib.orc_mass.restype = d
+    lib.orc_wss_sum.argtypes = [i64, P, d, P]
+    lib.orc_wss_sum.restype = d
+    if hasattr(lib, "orc_adj_run"):
+        _declare_adjoint(lib)
+    _lib = lib
+    return lib
+
+
+def _declare_adjoint(lib):
+    P, i64, i32, d = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
+    lib.orc_tangent_step.argtypes = [i64, P, P, d, d, P, i32, P, i64, P, P, P, P, P, P]
+    lib.orc_tangent_step.restype = ctypes.c_int
+    lib.orc_adjoint_step.argtypes = [i64, P, P, d, d, P, i32, P, i64, P, P, P, P, P]
+    lib.orc_adjoint_step.restype = ctypes.c_int
+    lib.orc_wss_grad.argtypes = [i64, P, d, P, d, P]
+    lib.orc_adj_run.argtypes = [i64, P, P, d, d, P, i32, P, i64, i64, i64, i64, P, P, P, P]
+    lib.orc_adj_run.restype = ctypes.c_int
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _c64(a, dtype=np.float64):
+    return None if a is None else np.ascontiguousarray(a, dtype=dtype)
+
+
+class Problem:
+    """A geometry plus the physics parameters the oracle needs, marshalled once."""
+
+    def __init__(self, geom, tau: float, rho0: float = 1.0, tables=None, phi=None):
+        self.n = int(geom.coords.shape[0])
+        self.coords = np.ascontiguousarray(geom.coords, dtype=np.int32)
+        self.nbr = np.ascontiguousarray(geom.nbr, dtype=np.int32)
+        self.tau = float(tau)
+        self.rho0 = float(rho0)
+        self.phi = _c64(phi)
+        self._tables = []
+        ios = (_Iolet * max(1, len(geom.iolets)))()
+        for k, io in enumerate(geom.iolets):
+            tab = tables[k] if tables is not None and tables[k] is not None else io.table
+            if tab is None:
+                tab = np.array([0.0 if io.kind == 0 else self.rho0])
+            tab = np.ascontiguousarray(tab, dtype=np.float64).reshape(-1)
+            self._tables.append(tab)
+            ios[k].kind = int(io.kind)
+            ios[k].role = int(io.role)
+            ios[k].centre[:] = [float(v) for v in io.centre]
+            ios[k].normal[:] = [float(v) for v in io.normal]
+            ios[k].radius = float(io.radius)
+            vd = getattr(io, "vdir", (0.0, 0.0, 0.0)) or (0.0, 0.0, 0.0)
+            ios[k].vdir[:] = [float(v) for v in vd]
+            ios[k].table = tab.ctypes.data_as(ctypes.c_void_p)
+            ios[k].table_len = tab.size
+        self.io = ios
+        self.n_io = len(geom.iolets)
+
+    # -- state ---------------------------------------------------------
+    def init(self, rho=None, u=None) -> np.ndarray:
+        f = np.empty((self.n, Q), dtype=np.float64)
+        _load().orc_init(self.n, _p(_c64(rho)), _p(_c64(u)), self.rho0, _p(f))
+        return f
+
+    def step(self, f, t: int, write_count: bool = False):
+        f = np.ascontiguousarray(f, dtype=np.float64)
+        F = np.full_like(f, np.nan)
+        flux = np.zeros(1)
+        wc = np.zeros((self.n, Q), dtype=np.int32) if write_count else None
+        rc = _load().orc_step(self.n, _p(self.coords), _p(self.nbr), self.tau, self.rho0, ctypes.byref(self.io),
+                              self.n_io, _p(self.phi), int(t), _p(f), _p(F), _p(flux), _p(wc))
+        if rc != 0:
+            raise ValueError("oracle step: bad link code")
+        return (F, float(flux[0]), wc) if write_count else (F, float(flux[0]))
+
+    def run(self, f, t0: int, nsteps: int):
+        """Advance f (in place) from t0 by nsteps; returns the summed boundary flux."""
+        assert f.dtype == np.float64 and f.flags.c_contiguous and f.shape == (self.n, Q)
+        work = np.empty_like(f)
+        flux = np.zeros(1)
+        rc = _load().orc_run(self.n, _p(self.coords), _p(self.nbr), self.tau, self.rho0, ctypes.byref(self.io),
+                             self.n_io, _p(self.phi), int(t0), int(nsteps), _p(f), _p(work), _p(flux))
+        if rc != 0:
+            raise ValueError("oracle run: bad link code")
+        return float(flux[0])
+
+    def macros(self, f):
+        rho = np.empty(self.n)
+        u = np.empty((self.n, 3))
+        wss = np.empty(self.n)
+        _load().orc_macros(self.n, _p(self.nbr), self.tau, _p(np.ascontiguousarray(f)), _p(rho), _p(u), _p(wss))
+        return rho, u, wss
+
+    def mass(self, f) -> float:
+        return float(_load().orc_mass(self.n, _p(np.ascontiguousarray(f))))
+
+    def wss_sum(self, f) -> float:
+        return float(_load().orc_wss_sum(self.n, _p(self.nbr), self.tau, _p(np.ascontiguousarray(f))))
+
+    def collide_all(self, f) -> np.ndarray:
+        out = np.empty_like(f)
+        for x in range(self.n):
+            out[x] = collide(f[x], self.tau)
+        return out
+
+
+# -- single-site functions -------------------------------------------------
+
+def lattice():
+    c = np.empty((Q, 3), dtype=np.int32)
+    w = np.empty(Q)
+    opp = np.empty(Q, dtype=np.int32)
+    _load().orc_lattice(_p(c), _p(w), _p(opp))
+    return c, w, opp
+
+
+def equilibrium(rho: float, u) -> np.ndarray:
+    out = np.empty(Q)
+    _load().orc_equilibrium(float(rho), _p(_c64(u)), _p(out))
+    return out
+
+
+def moments(f):
+    rho = np.zeros(1)
+    u = np.empty(3)
+    _load().orc_moments(_p(_c64(f)), _p(rho), _p(u))
+    return float(rho[0]), u
+
+
+def collide(f, tau: float) -> np.ndarray:
+    out = np.empty(Q)
+    _load().orc_collide(_p(_c64(f)), float(tau), _p(out))
+    return out

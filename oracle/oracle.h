@@ -1,0 +1,98 @@
+/*
+ * oracle.h -- plain FP64 CPU reference of the sparse D3Q19 LBGK update.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may include, link
+ * or call this code; only the test suite, the smoke check and the CPU
+ * baseline leg of the benchmark use it.  It shares no code, header, table or
+ * constant with the GPU library.
+ *
+ * What it computes (Zacharoudiou, McCullough, Coveney, "Development and
+ * performance of a HemeLB GPU code for human-scale blood flow simulation"):
+ *   - D3Q19 lattice, weights 1/3, 1/18, 1/36, c_s^2 = 1/3       (Sec. 2.2)
+ *   - BGK collision, eq. (3a); streaming, eq. (3b)               (Sec. 2.2)
+ *   - equilibrium, eq. (4), read with the usual 1/2 factors on the
+ *     second-order terms (the printed form lacks them; see the readings)
+ *   - density and momentum moments, eqs. (5), (6)
+ *   - mid-link bounce-back at walls                              (Sec. 2.3.1)
+ *   - Ladd velocity iolets and ghost-density pressure iolets     (Sec. 2.3.2)
+ *   - push order: collide, then scatter, with the boundary rules applied in
+ *     the same pass                                               (Sec. 3.1)
+ * Layout: array of structures f[x*19 + i], sites in input order.
+ *
+ * Extensions the paper does not define, each stated where it is used:
+ * wall shear stress, per-wall-site porosity, the mass-balance bookkeeping,
+ * and the tangent-linear / adjoint models of oracle_adjoint.c.
+ *
+ * Pins: see tests/test_oracle_*.py.  The velocity-iolet density choice
+ * (reference density rho0), the pressure-iolet ghost velocity (site velocity
+ * projected on the iolet normal) and the wall normal used by the shear stress
+ * are readings with no physical pin: parity unpinned for those three choices
+ * beyond both codes implementing the written definition.
+ */
+#ifndef HLB_ORACLE_H
+#define HLB_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ORC_Q 19
+#define ORC_WALL (-1) /* link code of a wall; iolet k is -(2+k) */
+
+typedef struct {
+  int32_t kind;      /* 0: velocity (Ladd), 1: pressure (ghost density) */
+  int32_t role;      /* 0: inlet, 1: outlet (classification only) */
+  double centre[3];  /* point on the iolet plane */
+  double normal[3];  /* unit normal pointing into the fluid */
+  double radius;     /* > 0: parabolic weight max(0, 1 - d^2/R^2); <= 0: weight 1 */
+  double vdir[3];    /* direction of the imposed velocity; all zero: normal */
+  const double *table; /* per-step amplitude A_k(s) or ghost density rho_k(s) */
+  int64_t table_len;   /* value at step s is table[s mod table_len] */
+} orc_iolet;
+
+/* Lattice constants as the oracle uses them (for the tests). */
+void orc_lattice(int32_t *c /*[19][3]*/, double *w /*[19]*/, int32_t *opp /*[19]*/);
+
+/* eq. (4) with the 1/2 factors. */
+void orc_equilibrium(double rho, const double *u, double *feq);
+/* eqs. (5), (6): rho = sum f, rho u = sum f c. */
+void orc_moments(const double *f, double *rho, double *u);
+/* eq. (3a) with dt = 1. */
+void orc_collide(const double *f, double tau, double *fout);
+
+/* f(x,0) = f^eq(rho(x), u(x)); rho, u may be NULL (rho0, 0).  Sec. 3.1 step 1. */
+void orc_init(int64_t n, const double *rho, const double *u, double rho0, double *f);
+
+/* One update t -> t+1 (push).  f: pre-collision state at t, F: state at t+1.
+ * phi: per-site porosity (read at wall links) or NULL.  flux_out: receives
+ * the mass the boundary rules added this step, sum over boundary links of
+ * (value filled in - post-collision value that left).  write_count: NULL, or
+ * an int32 array [n*19] that is incremented once per write of a slot.
+ * Returns 0, or -1 on a bad link code. */
+int orc_step(int64_t n, const int32_t *coords, const int32_t *nbr, double tau, double rho0,
+             const orc_iolet *io, int32_t n_io, const double *phi, int64_t t, const double *f,
+             double *F, double *flux_out, int32_t *write_count);
+
+/* nsteps updates starting at time t0; f holds the state at t0 on entry and at
+ * t0+nsteps on return (work: scratch of n*19 doubles).  *flux_sum (may be
+ * NULL) is increased by the boundary mass flux of every step. */
+int orc_run(int64_t n, const int32_t *coords, const int32_t *nbr, double tau, double rho0,
+            const orc_iolet *io, int32_t n_io, const double *phi, int64_t t0, int64_t nsteps,
+            double *f, double *work, double *flux_sum);
+
+/* Density, velocity and wall shear stress of state f (pre-collision).
+ * wss is 0 at sites without a wall link.  Any output may be NULL. */
+void orc_macros(int64_t n, const int32_t *nbr, double tau, const double *f, double *rho, double *u,
+                double *wss);
+
+/* Total mass sum_x sum_i f_i (compensated summation). */
+double orc_mass(int64_t n, const double *f);
+
+/* Sum of WSS over all sites with a wall link (compensated). */
+double orc_wss_sum(int64_t n, const int32_t *nbr, double tau, const double *f);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
