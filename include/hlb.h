@@ -1,0 +1,247 @@
+/*
+ * hlb.h -- C ABI of the MI355X (gfx950) sparse D3Q19 lattice-Boltzmann
+ * (LBGK) library.
+ *
+ * The method is the one of Zacharoudiou, McCullough and Coveney,
+ * "Development and performance of a HemeLB GPU code for human-scale blood
+ * flow simulation" (arXiv 2202.11770):
+ *   - D3Q19 lattice and single-relaxation-time (BGK) collision, eq. (3a),
+ *     followed by streaming, eq. (3b)                         (Sec. 2.2)
+ *   - equilibrium eq. (4) (with the standard 1/2 factors on the
+ *     second-order terms), moments eqs. (5)-(6)                (Sec. 2.2)
+ *   - mid-link bounce-back at walls                            (Sec. 2.3.1)
+ *   - velocity iolets by Ladd's corrected bounce-back and pressure iolets by
+ *     a ghost density                                          (Sec. 2.3.2)
+ *   - sites grouped by collision-streaming type, one wavefront-uniform
+ *     kernel per group, structure-of-arrays populations, f_old / f_new
+ *     swapped by pointer each step                             (Sec. 3.2.2-3.2.3)
+ * computed on the GPU as a pull (gather-then-collide) update over a sparse
+ * list of fluid sites ordered along a space-filling curve.
+ *
+ * Conventions (every function):
+ *   - returns hlb_status: HLB_OK (0) or a negative error code; the text of
+ *     the last failure on the calling thread is hlb_last_error().
+ *   - inputs are caller-owned and copied before return; the context owns all
+ *     device memory until hlb_destroy.
+ *   - site-indexed arrays are in the CALLER's site order (the order of
+ *     hlb_create's inputs), whatever order the library uses internally.
+ *   - a context is not thread-safe; distinct contexts are independent.
+ *   - host pointers are plain CPU memory; "device" pointers are GPU memory
+ *     of the current HIP device (e.g. torch tensors' data_ptr()).
+ *
+ * Lattice conventions shared with every producer of inputs:
+ *   velocity order, opposite directions adjacent (opp(i) = i+1 for odd i):
+ *     0 (0,0,0)
+ *     1 (+1,0,0)  2 (-1,0,0)  3 (0,+1,0)  4 (0,-1,0)  5 (0,0,+1)  6 (0,0,-1)
+ *     7 (+1,+1,0) 8 (-1,-1,0) 9 (+1,-1,0) 10 (-1,+1,0)
+ *     11 (+1,0,+1) 12 (-1,0,-1) 13 (+1,0,-1) 14 (-1,0,+1)
+ *     15 (0,+1,+1) 16 (0,-1,-1) 17 (0,+1,-1) 18 (0,-1,+1)
+ *   weights 1/3 (i=0), 1/18 (1-6), 1/36 (7-18); c_s^2 = 1/3; dx = dt = 1.
+ */
+#ifndef HLB_H
+#define HLB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hlb_ctx hlb_ctx; /* opaque, owned by the library */
+
+typedef enum {
+  HLB_OK = 0,
+  HLB_EINVAL = -1,   /* invalid argument; nothing was changed */
+  HLB_ENOMEM = -2,   /* device or host allocation failed, or above the budget */
+  HLB_EDEVICE = -3,  /* a HIP runtime call failed */
+  HLB_ESTATE = -4,   /* call not valid in the context's current state */
+  HLB_ENUMERIC = -5  /* a non-finite value was found in the state */
+} hlb_status;
+
+/* Storage of the 19 populations.  FP64 stores f_i in double and collides in
+ * double (the paper's variables); the shifted low-precision forms store the
+ * deviation f_i - w_i rho0 from the rest state in float / IEEE half (round
+ * to nearest even) and collide in float.  Mass-balance sums are FP64 in
+ * every form. */
+typedef enum { HLB_F64 = 0, HLB_F32_SHIFTED = 1, HLB_F16_SHIFTED = 2 } hlb_storage;
+
+/* Site types (Sec. 3.2.2: the six collision-streaming types). */
+enum {
+  HLB_SITE_BULK = 0,
+  HLB_SITE_WALL = 1,
+  HLB_SITE_INLET = 2,
+  HLB_SITE_OUTLET = 3,
+  HLB_SITE_INLET_WALL = 4,
+  HLB_SITE_OUTLET_WALL = 5
+};
+
+/* Neighbour-table codes: >= 0 a fluid site id, HLB_LINK_WALL a wall link,
+ * -(2+k) a link through iolet k. */
+#define HLB_LINK_WALL (-1)
+#define HLB_LINK_IOLET(k) (-(2 + (k)))
+
+/* Internal site order (all keep the six types grouped). */
+typedef enum {
+  HLB_ORDER_INPUT = 0,  /* caller order within each group */
+  HLB_ORDER_LEX = 1,    /* lexicographic (z, y, x) */
+  HLB_ORDER_MORTON = 2, /* Morton (Z-order) curve */
+  HLB_ORDER_BRICK = 3   /* Morton order of 4x4x4 bricks, lexicographic inside (default) */
+} hlb_order;
+
+enum { HLB_IOLET_VELOCITY = 0, HLB_IOLET_PRESSURE = 1 };
+enum { HLB_ROLE_INLET = 0, HLB_ROLE_OUTLET = 1 };
+
+/* One inlet or outlet ("iolet", Sec. 2.3.2).
+ * Velocity kind (Ladd): a population leaving site x along c_i through the
+ * iolet comes back as f'_i - 6 w_i rho0 (c_i . U), U = A_k(s) W(m) v_k, with
+ * m = x + c_i/2 the link midpoint, W(m) = max(0, 1 - d^2/R^2) where d is the
+ * distance of m from the iolet axis (centre, normal) (W = 1 if radius <= 0),
+ * and v_k = vdir (the normal if vdir is zero).
+ * Pressure kind (ghost density): it comes back as the equilibrium at density
+ * rho_k(s) and the site's velocity projected on the normal.
+ * A_k(s) / rho_k(s) is the iolet's table at s mod len (hlb_set_iolet_table);
+ * the update from time s to s+1 uses the value at s. */
+typedef struct {
+  int32_t kind;      /* HLB_IOLET_VELOCITY or HLB_IOLET_PRESSURE */
+  int32_t role;      /* HLB_ROLE_INLET or HLB_ROLE_OUTLET (selects the site type) */
+  double centre[3];  /* a point of the iolet plane, lattice units */
+  double normal[3];  /* unit normal pointing into the fluid */
+  double radius;     /* profile radius R; <= 0: uniform weight */
+  double vdir[3];    /* direction of the imposed velocity; zero vector: normal */
+} hlb_iolet;
+
+typedef struct {
+  int32_t storage;     /* hlb_storage (default HLB_F64) */
+  int32_t order;       /* hlb_order (default HLB_ORDER_BRICK) */
+  int32_t xcd_remap;   /* 1 (default): give each of the 8 XCDs a contiguous
+                          range of the site list; 0: plain block order */
+  int32_t reserved;    /* must be 0 */
+  double rho0;         /* reference density (default 1.0) */
+  int64_t max_device_bytes; /* 0: no limit; otherwise HLB_ENOMEM above it */
+} hlb_options;
+
+/* Fill *opt with the defaults. */
+hlb_status hlb_default_options(hlb_options *opt);
+
+/* Create a simulation (Sec. 3.2.1: device set-up).
+ *   n_sites   number of fluid sites, 1 <= n_sites < 2^31 - 2^12
+ *   coords    [n][3] int32 lattice coordinates, each in [0, 2^20)
+ *   site_type [n] uint8, HLB_SITE_*; must agree with the link codes
+ *   nbr       [n][19] int32 push-direction table: nbr[x][i] = id of the site
+ *             at coords[x] + c_i, HLB_LINK_WALL or HLB_LINK_IOLET(k);
+ *             nbr[x][0] == x; must be symmetric
+ *             (nbr[x][i] = y >= 0 implies nbr[y][opp(i)] = x)
+ *   tau       relaxation time, > 1/2 (eq. (8): viscosity (tau - 1/2)/3)
+ *   iolets    [n_iolets] descriptors (may be NULL if n_iolets == 0)
+ *   opt       options or NULL for the defaults
+ *   out       receives the context
+ * The state starts at rest (f = f^eq(rho0, 0)) at time t = 0; velocity
+ * tables start as {0}, pressure tables as {rho0}.
+ * Errors: HLB_EINVAL (any rule above broken; message names the first
+ * offending site/link), HLB_ENOMEM, HLB_EDEVICE. */
+hlb_status hlb_create(int64_t n_sites, const int32_t *coords, const uint8_t *site_type,
+                      const int32_t *nbr, double tau, const hlb_iolet *iolets, int32_t n_iolets,
+                      const hlb_options *opt, hlb_ctx **out);
+
+/* Release all device and host memory of the context (NULL is accepted). */
+hlb_status hlb_destroy(hlb_ctx *ctx);
+
+/* Run the context's work on a caller-owned HIP stream (hipStream_t); NULL
+ * restores the context's own stream.  The stream must outlive its use. */
+hlb_status hlb_set_stream(hlb_ctx *ctx, void *hip_stream);
+
+/* Per-step table of iolet k: A_k(s) (velocity) or rho_k(s) (pressure),
+ * value at step s = values[s mod len]; len >= 1, values finite (host). */
+hlb_status hlb_set_iolet_table(hlb_ctx *ctx, int32_t k, const double *values, int64_t len);
+
+/* Porosity phi in [0,1] per site (host, [n], caller order; read at sites
+ * with wall links only): a wall link returns (1 - phi) f'_i + phi w_i rho0,
+ * i.e. a fraction phi leaks to a reservoir at rest density.  NULL removes
+ * the porosity (plain bounce-back).  Not a rule of the paper. */
+hlb_status hlb_set_porosity(hlb_ctx *ctx, const double *phi);
+
+/* Reset the state to f = f^eq(rho(x), u(x)) (Sec. 3.1, step 1) at time t0.
+ * rho [n] and u [n][3] are host arrays in caller order, or NULL for rho0 and
+ * zero velocity.  Resets the mass-balance bookkeeping. */
+hlb_status hlb_init_equilibrium(hlb_ctx *ctx, const double *rho, const double *u, int64_t t0);
+
+/* Advance n >= 0 steps (t -> t + n), asynchronously on the context stream.
+ * Each step: pull-gather with boundary rules, then BGK collision, for all
+ * site groups; then the f_old / f_new pointer swap. */
+hlb_status hlb_step(hlb_ctx *ctx, int64_t n);
+
+/* Density, velocity [n][3] and wall shear stress of the state at the
+ * current time t (pre-collision populations), in caller order.  Any output
+ * may be NULL.  Wall shear stress (not defined by the paper) is the
+ * tangential part of the traction sigma n, sigma = -(1 - 1/(2 tau)) times
+ * the non-equilibrium second moment, n the normalised sum of the site's
+ * wall-link directions; 0 at sites without wall links.
+ * hlb_macros: host outputs, synchronises.  hlb_macros_device: device
+ * outputs (double), asynchronous on the context stream. */
+hlb_status hlb_macros(hlb_ctx *ctx, double *rho, double *u, double *wss);
+hlb_status hlb_macros_device(hlb_ctx *ctx, void *rho, void *u, void *wss);
+
+/* Pre-collision populations f_i(x, t) as [n][19] FP64, caller order (host,
+ * synchronises). */
+hlb_status hlb_get_state(hlb_ctx *ctx, double *f);
+/* Set f_i(x, t) (host [n][19] FP64, caller order) and the time t.  Resets
+ * the mass-balance bookkeeping. */
+hlb_status hlb_set_state(hlb_ctx *ctx, const double *f, int64_t t);
+
+/* Total mass M(t) = sum_x sum_i f_i (FP64 reduction) and the balance
+ * residual R(t) = M(t) - M(t0) - (mass added by the boundary rules since
+ * t0), t0 the last (re)initialisation.  Synchronises.  HLB_ENUMERIC if M is
+ * not finite. */
+hlb_status hlb_mass_balance(hlb_ctx *ctx, double *mass, double *residual);
+
+/* Current time step t. */
+hlb_status hlb_time(const hlb_ctx *ctx, int64_t *t);
+
+typedef struct {
+  int64_t n_sites;          /* fluid sites */
+  int64_t n_padded;         /* sites incl. padding that keeps each group wave-aligned */
+  int64_t group_sites[6];   /* sites per group: bulk+wall, inlet, outlet,
+                               inlet+wall, outlet+wall, (unused) */
+  int32_t storage;          /* hlb_storage */
+  int32_t order;            /* hlb_order */
+  double bytes_per_lup;     /* algorithmic HBM bytes per lattice-site update */
+  int64_t device_bytes;     /* device memory held by the context */
+} hlb_info_t;
+hlb_status hlb_info(const hlb_ctx *ctx, hlb_info_t *info);
+
+/* Kernel timing (HIP events around each launch of the bulk kernel) while
+ * enabled; hlb_stats reports the steps timed and the mean bulk-kernel and
+ * whole-step durations in milliseconds. */
+hlb_status hlb_set_timing(hlb_ctx *ctx, int32_t enable);
+typedef struct {
+  int64_t steps;            /* steps timed since timing was enabled */
+  double bulk_kernel_ms;    /* mean duration of the bulk+wall kernel */
+  double iolet_kernel_ms;   /* mean duration of the iolet kernel */
+  double step_ms;           /* mean wall time of a whole step on the stream */
+} hlb_stats_t;
+hlb_status hlb_stats(hlb_ctx *ctx, hlb_stats_t *stats);
+
+/* Device snapshots of the whole state (for checkpointing schedules).
+ * hlb_snapshot_alloc reserves n_slots slots (frees previous ones). */
+hlb_status hlb_snapshot_alloc(hlb_ctx *ctx, int32_t n_slots);
+hlb_status hlb_snapshot_save(hlb_ctx *ctx, int32_t slot);
+hlb_status hlb_snapshot_restore(hlb_ctx *ctx, int32_t slot);
+
+/* Bit-exact host copy of the state (both population buffers, time and
+ * bookkeeping): hlb_state_bytes gives the size; save writes it to host
+ * memory, load restores it.  Synchronise. */
+hlb_status hlb_state_bytes(const hlb_ctx *ctx, int64_t *bytes);
+hlb_status hlb_state_save(hlb_ctx *ctx, void *host_buf);
+hlb_status hlb_state_load(hlb_ctx *ctx, const void *host_buf);
+
+/* Wait for all work queued on the context stream. */
+hlb_status hlb_sync(hlb_ctx *ctx);
+
+/* Message of the last failure on this thread ("" if none). */
+const char *hlb_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HLB_H */

@@ -62,6 +62,8 @@ def _load():
     lib.orc_mass.restype = d
     lib.orc_wss_sum.argtypes = [i64, P, d, P]
     lib.orc_wss_sum.restype = d
+    lib.orc_threads.argtypes = []
+    lib.orc_threads.restype = ctypes.c_int32
     if hasattr(lib, "orc_adj_run"):
         _declare_adjoint(lib)
     _lib = lib
@@ -163,6 +165,10 @@ class Problem:
         for x in range(self.n):
             out[x] = collide(f[x], self.tau)
         return out
+
+
+def threads() -> int:
+    return int(_load().orc_threads())
 
 
 # -- single-site functions -------------------------------------------------

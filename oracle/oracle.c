@@ -277,6 +277,14 @@ double orc_mass(int64_t n, const double *f) {
   return acc.s;
 }
 
+int32_t orc_threads(void) {
+#ifdef _OPENMP
+  return (int32_t)omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
 double orc_wss_sum(int64_t n, const int32_t *nbr, double tau, const double *f) {
   kahan acc = {0.0, 0.0};
   for (int64_t x = 0; x < n; ++x) kadd(&acc, site_wss(f + ORC_Q * x, nbr + ORC_Q * x, tau));

@@ -89,6 +89,9 @@ void orc_macros(int64_t n, const int32_t *nbr, double tau, const double *f, doub
 /* Total mass sum_x sum_i f_i (compensated summation). */
 double orc_mass(int64_t n, const double *f);
 
+/* Number of OpenMP threads the oracle uses. */
+int32_t orc_threads(void);
+
 /* Sum of WSS over all sites with a wall link (compensated). */
 double orc_wss_sum(int64_t n, const int32_t *nbr, double tau, const double *f);
 

@@ -1,0 +1,562 @@
+// gfx950 kernels of the sparse D3Q19 LBGK update (pull scheme).
+//
+// One thread owns one fluid site.  Populations live in two structure-of-
+// arrays buffers (Sec. 3.2.3: SoA on the GPU; f_old / f_new swapped by
+// pointer), each [19][np] of the storage type.  FP64 stores f_i itself, as
+// the paper does; the FP32 / FP16 forms store the deviation f_i - w_i rho0
+// from the rest state and collide in FP32.  A step gathers the 19
+// post-collision populations that stream into the site (eq. (3b) read
+// backwards: the pull order the paper proposes in its future-work section),
+// substitutes the boundary rules for links that cross a wall or an iolet
+// (Sec. 2.3), collides (eq. (3a) with eq. (4)) and stores the 19 results at
+// the site's own, coalesced, slots.
+//
+// Sites are grouped by collision-streaming type (Sec. 3.2.2): positions
+// [0, n0) hold the merged bulk+wall group, handled by k_step_bulk with a
+// branch-free address select for bounce-back; the four iolet groups follow,
+// each starting on a 256-site boundary, and are handled by k_step_iolet.
+//
+// The method is bound by HBM bandwidth (~0.7 flop per byte in FP64), so
+// nothing here uses the matrix cores.
+
+#include <type_traits>
+
+#include "hlb_internal.h"
+
+namespace hlb {
+namespace {
+
+constexpr int Q = 19;
+constexpr int kBlock = 256;
+
+// D3Q19, opposite directions adjacent (the input convention of hlb.h).
+__host__ __device__ constexpr int cx(int i) {
+  constexpr int v[Q] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+  return v[i];
+}
+__host__ __device__ constexpr int cy(int i) {
+  constexpr int v[Q] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+  return v[i];
+}
+__host__ __device__ constexpr int cz(int i) {
+  constexpr int v[Q] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+  return v[i];
+}
+__host__ __device__ constexpr int opp(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
+// weights 1/3, 1/18, 1/36 (Sec. 2.2)
+template <typename C>
+__host__ __device__ constexpr C wgt(int i) {
+  return i == 0 ? C(1) / C(3) : (i <= 6 ? C(1) / C(18) : C(1) / C(36));
+}
+
+// Compute type: double for FP64 storage, float for the shifted FP32/FP16 forms.
+template <typename T>
+struct Acc { using type = float; };
+template <>
+struct Acc<double> { using type = double; };
+// Stored value s_i = f_i - shift_i, shift_i = w_i rho0 for the shifted forms
+// and 0 for FP64; rest_i is the stored value of the rest state.
+template <typename T>
+constexpr bool kShifted = !std::is_same<T, double>::value;
+template <bool SH, typename C>
+__device__ inline C shift(int i, C rho0) {
+  return SH ? wgt<C>(i) * rho0 : C(0);
+}
+template <bool SH, typename C>
+__device__ inline C rest(int i, C rho0) {
+  return SH ? C(0) : wgt<C>(i) * rho0;
+}
+
+__device__ inline double ld(const double *p) { return *p; }
+__device__ inline float ld(const float *p) { return *p; }
+__device__ inline float ld(const _Float16 *p) { return static_cast<float>(*p); }
+__device__ inline void st(double *p, double v) { *p = v; }
+__device__ inline void st(float *p, float v) { *p = v; }
+__device__ inline void st(_Float16 *p, float v) { *p = static_cast<_Float16>(v); }  // round to nearest even
+
+// Give each XCD (workgroups are dealt to the 8 XCDs round-robin) one
+// contiguous range of blocks, so that neighbouring sites share an L2.
+__device__ inline int64_t block_id(bool remap) {
+  const int64_t b = blockIdx.x;
+  if (!remap) return b;
+  const int64_t G = gridDim.x, q = G >> 3, r = G & 7, x = b & 7, m = b >> 3;
+  return x * q + (x < r ? x : r) + m;
+}
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Moments (eqs. (5), (6)) of stored values s: rho = sum f, j = sum f c.
+// Sums run in ascending i.  For the shifted forms rho = rho0 + sum s.
+template <bool SH, typename C>
+__device__ inline void moments(const C (&s)[Q], C rho0, C &dr, C &rho, C &jx, C &jy, C &jz) {
+  dr = 0;
+  jx = 0;
+  jy = 0;
+  jz = 0;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    dr += s[i];
+    if (cx(i)) jx += cx(i) > 0 ? s[i] : -s[i];
+    if (cy(i)) jy += cy(i) > 0 ? s[i] : -s[i];
+    if (cz(i)) jz += cz(i) > 0 ? s[i] : -s[i];
+  }
+  rho = SH ? rho0 + dr : dr;
+}
+
+// Equilibrium eq. (4) (1/2 factors on the second-order terms) in the stored
+// representation:  f_eq = w rho (1 + 3 c.u + 9/2 (c.u)^2 - 3/2 u.u);
+// shifted: f_eq - w rho0 = w ((rho - rho0) + rho (3 c.u + 9/2 (c.u)^2 - 3/2 u.u)).
+template <bool SH, typename C>
+__device__ inline C s_eq(int i, C rho, C rho0, C ux, C uy, C uz, C usq15) {
+  const C cu = C(cx(i)) * ux + C(cy(i)) * uy + C(cz(i)) * uz;
+  const C q = C(3) * cu + C(4.5) * cu * cu - usq15;
+  return SH ? wgt<C>(i) * ((rho - rho0) + rho * q) : wgt<C>(i) * rho * (C(1) + q);
+}
+
+// BGK collision, eq. (3a) with dt = 1: s' = s + omega (s_eq - s).
+template <bool SH, typename C>
+__device__ inline void collide(C (&s)[Q], C omega, C rho0) {
+  C dr, rho, jx, jy, jz;
+  moments<SH>(s, rho0, dr, rho, jx, jy, jz);
+  const C inv = C(1) / rho;
+  const C ux = jx * inv, uy = jy * inv, uz = jz * inv;
+  const C usq = C(1.5) * (ux * ux + uy * uy + uz * uz);
+#pragma unroll
+  for (int i = 0; i < Q; ++i) s[i] = s[i] + omega * (s_eq<SH>(i, rho, rho0, ux, uy, uz, usq) - s[i]);
+}
+
+struct GatherArgs {
+  const int32_t *nbr;
+  int64_t np;
+  int64_t io_begin;
+  int64_t nio;
+  const double *corr;
+  const IoletDev *io;
+  const double *tables;
+  int64_t t;           // the update t -> t+1 uses the tables at t
+  const double *phi;   // porosity or null
+  double rho0;
+};
+
+// Pre-collision populations of site p at time t+1, gathered from the
+// post-collision buffer A of time t (stored values s = f - off), with the
+// boundary rules (Sec. 2.3) for links that do not reach a fluid site:
+//   wall (mid-link bounce-back):  f_i = f'_opp(i)(p); a porous wall site
+//                                 returns (1 - phi) f'_opp(i) + phi w_i rho0
+//   velocity iolet (Ladd):        f_i = f'_opp(i)(p) + 6 w_i rho0 (c_i.U(m)),
+//                                 m = x - c_i/2, U = A_k(t) W(m) v_k
+//   pressure iolet (ghost rho):   f_i = f_i^eq(rho_k(t), (u.n) n),
+//                                 u the site's velocity at time t
+// Returns the mass the boundary rules added (filled - reflected).
+// IOLET = false: the site has only fluid and wall links.
+template <bool IOLET, bool POROUS, bool SH, typename T, typename C>
+__device__ inline C gather(const T *__restrict__ A, int64_t p, const GatherArgs &a, C (&g)[Q]) {
+  const int64_t np = a.np;
+  C flux = 0;
+  if constexpr (!IOLET) {
+    g[0] = ld(A + p);
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+      const int32_t j = a.nbr[(int64_t)(i - 1) * np + p];
+      // branch-free: fluid source j, or the site's own reflected slot
+      const T *src = (j >= 0) ? (A + (int64_t)i * np + j) : (A + (int64_t)opp(i) * np + p);
+      C v = ld(src);
+      if constexpr (POROUS) {
+        if (j < 0) {
+          const C nv = v - C(a.phi[p]) * (v - rest<SH, C>(i, C(a.rho0)));
+          flux += nv - v;
+          v = nv;
+        }
+      }
+      g[i] = v;
+    }
+  } else {
+    C own[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) own[i] = ld(A + (int64_t)i * np + p);
+    // velocity at time t: moments of the site's own post-collision state
+    // (the collision conserves rho and rho u)
+    C dr, rho, jx, jy, jz;
+    moments<SH>(own, C(a.rho0), dr, rho, jx, jy, jz);
+    const C ux = jx / rho, uy = jy / rho, uz = jz / rho;
+    g[0] = own[0];
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+      const int32_t code = a.nbr[(int64_t)(i - 1) * np + p];
+      if (code >= 0) {
+        g[i] = ld(A + (int64_t)i * np + code);
+        continue;
+      }
+      const C back = own[opp(i)];
+      C v;
+      if (code == HLB_LINK_WALL) {
+        v = back;
+        if constexpr (POROUS) v = back - C(a.phi[p]) * (back - rest<SH, C>(i, C(a.rho0)));
+      } else {
+        const IoletDev K = a.io[-code - 2];
+        const double val = a.tables[K.tab_off + a.t % K.tab_len];
+        if (K.kind == HLB_IOLET_VELOCITY) {
+          v = back + C(a.corr[(int64_t)(i - 1) * a.nio + (p - a.io_begin)] * val);
+        } else {
+          const C un = ux * C(K.n[0]) + uy * C(K.n[1]) + uz * C(K.n[2]);
+          const C gx = un * C(K.n[0]), gy = un * C(K.n[1]), gz = un * C(K.n[2]);
+          const C uu = C(1.5) * (gx * gx + gy * gy + gz * gz);
+          v = s_eq<SH>(i, C(val), C(a.rho0), gx, gy, gz, uu);
+        }
+      }
+      flux += v - back;
+      g[i] = v;
+    }
+  }
+  return flux;
+}
+
+// ---------------------------------------------------------------- step ----
+
+template <typename T, bool POROUS>
+__global__ __launch_bounds__(kBlock) void k_step_bulk(const T *__restrict__ A, T *__restrict__ B,
+                                                      GatherArgs a, int64_t n0, int remap,
+                                                      typename Acc<T>::type omega, double *acc) {
+  using C = typename Acc<T>::type;
+  const int64_t p = block_id(remap) * kBlock + threadIdx.x;
+  C flux = 0;
+  if (p < n0) {
+    C g[Q];
+    flux = gather<false, POROUS, kShifted<T>>(A, p, a, g);
+    collide<kShifted<T>>(g, omega, C(a.rho0));
+#pragma unroll
+    for (int i = 0; i < Q; ++i) st(B + (int64_t)i * a.np + p, g[i]);
+  }
+  if constexpr (POROUS) {
+    const double s = wave_sum(double(flux));
+    if ((threadIdx.x & 63) == 0 && s != 0.0) atomicAdd(acc, s);
+  }
+}
+
+template <typename T, bool POROUS>
+__global__ __launch_bounds__(kBlock) void k_step_iolet(const T *__restrict__ A, T *__restrict__ B,
+                                                       GatherArgs a, const int32_t *__restrict__ order,
+                                                       typename Acc<T>::type omega, double *acc) {
+  using C = typename Acc<T>::type;
+  const int64_t p = a.io_begin + (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  C flux = 0;
+  if (p < a.np && order[p] >= 0) {
+    C g[Q];
+    flux = gather<true, POROUS, kShifted<T>>(A, p, a, g);
+    collide<kShifted<T>>(g, omega, C(a.rho0));
+#pragma unroll
+    for (int i = 0; i < Q; ++i) st(B + (int64_t)i * a.np + p, g[i]);
+  }
+  const double s = wave_sum(double(flux));
+  if ((threadIdx.x & 63) == 0 && s != 0.0) atomicAdd(acc, s);
+}
+
+// ------------------------------------------------------- init / state ----
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_init_eq(T *__restrict__ A, T *__restrict__ B,
+                                                    const int32_t *__restrict__ order, int64_t np,
+                                                    const double *__restrict__ staging, double rho0) {
+  const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (p >= np) return;
+  const int32_t id = order[p];
+  constexpr bool SH = kShifted<T>;
+  double g[Q];
+  if (id < 0) {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) g[i] = 0.0;
+  } else if (staging == nullptr) {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) g[i] = rest<SH>(i, rho0);
+  } else {
+    const double rho = staging[4 * (int64_t)id], ux = staging[4 * (int64_t)id + 1],
+                 uy = staging[4 * (int64_t)id + 2], uz = staging[4 * (int64_t)id + 3];
+    const double usq = 1.5 * (ux * ux + uy * uy + uz * uz);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) g[i] = s_eq<SH>(i, rho, rho0, ux, uy, uz, usq);
+  }
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    st(A + (int64_t)i * np + p, static_cast<typename Acc<T>::type>(g[i]));
+    st(B + (int64_t)i * np + p, static_cast<typename Acc<T>::type>(g[i]));
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_set_state(T *__restrict__ Pre, T *__restrict__ Post,
+                                                      const int32_t *__restrict__ order, int64_t np,
+                                                      const double *__restrict__ staging, double rho0,
+                                                      typename Acc<T>::type omega) {
+  using C = typename Acc<T>::type;
+  const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (p >= np) return;
+  const int32_t id = order[p];
+  constexpr bool SH = kShifted<T>;
+  C g[Q];
+#pragma unroll
+  for (int i = 0; i < Q; ++i)
+    g[i] = id < 0 ? C(0) : C(staging[(int64_t)id * Q + i] - shift<SH>(i, rho0));
+#pragma unroll
+  for (int i = 0; i < Q; ++i) st(Pre + (int64_t)i * np + p, g[i]);
+  if (id < 0) return;
+  collide<SH>(g, omega, C(rho0));
+#pragma unroll
+  for (int i = 0; i < Q; ++i) st(Post + (int64_t)i * np + p, g[i]);
+}
+
+// --------------------------------------------------------------- macros ----
+
+// Density, velocity, wall shear stress (or the populations) of the
+// pre-collision state at time t, in FP64, written per caller id.
+template <typename T, bool POROUS>
+__global__ __launch_bounds__(kBlock) void k_macros(const T *__restrict__ A, GatherArgs a,
+                                                   const int32_t *__restrict__ order, int direct,
+                                                   double tau, double *rho_o, double *u_o,
+                                                   double *wss_o, double *f_o) {
+  const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (p >= a.np) return;
+  const int32_t id = order[p];
+  if (id < 0) return;
+  constexpr bool SH = kShifted<T>;
+  double g[Q];
+  if (direct) {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) g[i] = ld(A + (int64_t)i * a.np + p);
+  } else if (p < a.io_begin) {
+    gather<false, POROUS, SH>(A, p, a, g);
+  } else {
+    gather<true, POROUS, SH>(A, p, a, g);
+  }
+  if (f_o) {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) f_o[(int64_t)id * Q + i] = g[i] + shift<SH>(i, a.rho0);
+    return;
+  }
+  double dr, rho, jx, jy, jz;
+  moments<SH>(g, a.rho0, dr, rho, jx, jy, jz);
+  const double ux = jx / rho, uy = jy / rho, uz = jz / rho;
+  if (rho_o) rho_o[id] = rho;
+  if (u_o) {
+    u_o[3 * (int64_t)id] = ux;
+    u_o[3 * (int64_t)id + 1] = uy;
+    u_o[3 * (int64_t)id + 2] = uz;
+  }
+  if (!wss_o) return;
+  // wall normal: normalised sum of the directions whose links hit a wall;
+  // pull entry i describes the link leaving along opp(i) = -c_i
+  double nx = 0, ny = 0, nz = 0;
+  bool any = false;
+#pragma unroll
+  for (int i = 1; i < Q; ++i) {
+    if (a.nbr[(int64_t)(i - 1) * a.np + p] == HLB_LINK_WALL) {
+      any = true;
+      nx -= cx(i);
+      ny -= cy(i);
+      nz -= cz(i);
+    }
+  }
+  double w = 0.0;
+  const double nn = sqrt(nx * nx + ny * ny + nz * nz);
+  if (any && nn > 0.0) {
+    nx /= nn;
+    ny /= nn;
+    nz /= nn;
+    const double usq = 1.5 * (ux * ux + uy * uy + uz * uz);
+    double pxx = 0, pyy = 0, pzz = 0, pxy = 0, pxz = 0, pyz = 0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      // non-equilibrium part f - f_eq (the same in either representation)
+      const double d = g[i] - s_eq<SH>(i, rho, a.rho0, ux, uy, uz, usq);
+      pxx += d * cx(i) * cx(i);
+      pyy += d * cy(i) * cy(i);
+      pzz += d * cz(i) * cz(i);
+      pxy += d * cx(i) * cy(i);
+      pxz += d * cx(i) * cz(i);
+      pyz += d * cy(i) * cz(i);
+    }
+    const double fac = -(1.0 - 1.0 / (2.0 * tau));
+    const double tx = fac * (pxx * nx + pxy * ny + pxz * nz);
+    const double ty = fac * (pxy * nx + pyy * ny + pyz * nz);
+    const double tz = fac * (pxz * nx + pyz * ny + pzz * nz);
+    const double tn = tx * nx + ty * ny + tz * nz;
+    const double sx = tx - tn * nx, sy = ty - tn * ny, sz = tz - tn * nz;
+    w = sqrt(sx * sx + sy * sy + sz * sz);
+  }
+  wss_o[id] = w;
+}
+
+// ----------------------------------------------------------------- mass ----
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_mass_partial(const T *__restrict__ A,
+                                                         const int32_t *__restrict__ order, int64_t np,
+                                                         double *partial) {
+  __shared__ double red[kBlock / 64];
+  double s = 0.0;
+  for (int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x; p < np; p += (int64_t)gridDim.x * kBlock) {
+    if (order[p] < 0) continue;
+    double q = 0.0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) q += ld(A + (int64_t)i * np + p);
+    s += q;
+  }
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double b = 0.0;
+    for (int w = 0; w < kBlock / 64; ++w) b += red[w];
+    partial[1 + blockIdx.x] = b;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_mass_final(double *partial, int64_t nparts) {
+  __shared__ double red[kBlock / 64];
+  double s = 0.0;
+  for (int64_t k = threadIdx.x; k < nparts; k += kBlock) s += partial[1 + k];
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double b = 0.0;
+    for (int w = 0; w < kBlock / 64; ++w) b += red[w];
+    partial[0] = b;
+  }
+}
+
+__global__ void k_zero(double *p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0.0;
+}
+
+GatherArgs make_args(const LaunchCfg &cfg, const Layout &L, const DevPtrs &d, int64_t t) {
+  GatherArgs a;
+  a.nbr = d.nbr;
+  a.np = L.np;
+  a.io_begin = L.io_begin;
+  a.nio = L.nio;
+  a.corr = d.corr;
+  a.io = d.io;
+  a.tables = d.tables;
+  a.t = t;
+  a.phi = cfg.porous ? d.phi : nullptr;
+  a.rho0 = cfg.rho0;
+  return a;
+}
+
+inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+template <typename T>
+hipError_t step_impl(const LaunchCfg &cfg, const Layout &L, const DevPtrs &d, int src, int64_t t,
+                     hipStream_t s, hipEvent_t e0, hipEvent_t e1, hipEvent_t e2) {
+  using C = typename Acc<T>::type;
+  const T *A = static_cast<const T *>(d.f[src]);
+  T *B = static_cast<T *>(d.f[1 - src]);
+  const GatherArgs a = make_args(cfg, L, d, t);
+  const C omega = C(1.0 / cfg.tau);
+  const int64_t n0 = L.gcnt[0];
+  hipError_t er;
+  if (e0 && (er = hipEventRecord(e0, s)) != hipSuccess) return er;
+  if (n0 > 0) {
+    if (cfg.porous)
+      k_step_bulk<T, true><<<blocks_for(n0), kBlock, 0, s>>>(A, B, a, n0, cfg.xcd_remap, omega, d.acc);
+    else
+      k_step_bulk<T, false><<<blocks_for(n0), kBlock, 0, s>>>(A, B, a, n0, cfg.xcd_remap, omega, d.acc);
+  }
+  if (e1 && (er = hipEventRecord(e1, s)) != hipSuccess) return er;
+  if (L.nio > 0) {
+    if (cfg.porous)
+      k_step_iolet<T, true><<<blocks_for(L.nio), kBlock, 0, s>>>(A, B, a, d.order, omega, d.acc);
+    else
+      k_step_iolet<T, false><<<blocks_for(L.nio), kBlock, 0, s>>>(A, B, a, d.order, omega, d.acc);
+  }
+  if (e2 && (er = hipEventRecord(e2, s)) != hipSuccess) return er;
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t macros_impl(const LaunchCfg &cfg, const Layout &L, const DevPtrs &d, int src, bool direct,
+                       int64_t t_prev, double *rho, double *u, double *wss, double *f_out,
+                       hipStream_t s) {
+  const T *A = static_cast<const T *>(d.f[src]);
+  const GatherArgs a = make_args(cfg, L, d, t_prev < 0 ? 0 : t_prev);
+  if (cfg.porous)
+    k_macros<T, true><<<blocks_for(L.np), kBlock, 0, s>>>(A, a, d.order, direct ? 1 : 0, cfg.tau, rho, u,
+                                                          wss, f_out);
+  else
+    k_macros<T, false><<<blocks_for(L.np), kBlock, 0, s>>>(A, a, d.order, direct ? 1 : 0, cfg.tau, rho, u,
+                                                           wss, f_out);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t init_impl(const LaunchCfg &cfg, const Layout &L, const DevPtrs &d, const double *staging,
+                     hipStream_t s) {
+  k_init_eq<T><<<blocks_for(L.np), kBlock, 0, s>>>(static_cast<T *>(d.f[0]), static_cast<T *>(d.f[1]),
+                                                   d.order, L.np, staging, cfg.rho0);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t set_state_impl(const LaunchCfg &cfg, const Layout &L, const DevPtrs &d, int pre,
+                          const double *staging, hipStream_t s) {
+  using C = typename Acc<T>::type;
+  k_set_state<T><<<blocks_for(L.np), kBlock, 0, s>>>(static_cast<T *>(d.f[pre]), static_cast<T *>(d.f[1 - pre]),
+                                                     d.order, L.np, staging, cfg.rho0, C(1.0 / cfg.tau));
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t mass_impl(const Layout &L, const DevPtrs &d, int src, hipStream_t s) {
+  int64_t nb = blocks_for(L.np);
+  if (nb > d.partial_len - 1) nb = d.partial_len - 1;
+  k_mass_partial<T><<<(unsigned)nb, kBlock, 0, s>>>(static_cast<const T *>(d.f[src]), d.order, L.np, d.partial);
+  k_mass_final<<<1, kBlock, 0, s>>>(d.partial, nb);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+#define HLB_DISPATCH(storage, CALL)                       \
+  switch (storage) {                                      \
+    case HLB_F64: { using T = double; return CALL; }      \
+    case HLB_F32_SHIFTED: { using T = float; return CALL; } \
+    case HLB_F16_SHIFTED: { using T = _Float16; return CALL; } \
+    default: return hipErrorInvalidValue;                 \
+  }
+
+hipError_t launch_step(const LaunchCfg &cfg, const Layout &L, const DevPtrs &d, int src, int64_t t,
+                       hipStream_t s, hipEvent_t e0, hipEvent_t e1, hipEvent_t e2) {
+  HLB_DISPATCH(cfg.storage, step_impl<T>(cfg, L, d, src, t, s, e0, e1, e2));
+}
+
+hipError_t launch_init_eq(const LaunchCfg &cfg, const Layout &L, const DevPtrs &d, const double *staging,
+                          hipStream_t s) {
+  HLB_DISPATCH(cfg.storage, init_impl<T>(cfg, L, d, staging, s));
+}
+
+hipError_t launch_macros(const LaunchCfg &cfg, const Layout &L, const DevPtrs &d, int src, bool direct,
+                         int64_t t_prev, double *rho, double *u, double *wss, double *f_out, hipStream_t s) {
+  HLB_DISPATCH(cfg.storage, macros_impl<T>(cfg, L, d, src, direct, t_prev, rho, u, wss, f_out, s));
+}
+
+hipError_t launch_set_state(const LaunchCfg &cfg, const Layout &L, const DevPtrs &d, int pre,
+                            const double *staging, hipStream_t s) {
+  HLB_DISPATCH(cfg.storage, set_state_impl<T>(cfg, L, d, pre, staging, s));
+}
+
+hipError_t launch_zero(double *p, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  k_zero<<<blocks_for(n), kBlock, 0, s>>>(p, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_mass(const LaunchCfg &cfg, const Layout &L, const DevPtrs &d, int src, hipStream_t s) {
+  HLB_DISPATCH(cfg.storage, mass_impl<T>(L, d, src, s));
+}
+
+}  // namespace hlb

@@ -1,0 +1,869 @@
+// Host runtime of the C ABI in hlb.h: input validation, grouping of sites by
+// collision-streaming type, space-filling-curve ordering, construction of
+// the pull neighbour table and iolet link coefficients, device memory, time
+// bookkeeping, snapshots and error reporting.  All arithmetic of the update
+// itself is in hlb_kernels.hip.
+
+#include <hip/hip_runtime.h>
+#include <omp.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "hlb.h"
+#include "hlb_internal.h"
+
+using namespace hlb;
+
+namespace {
+
+thread_local std::string g_err;
+
+hlb_status fail(hlb_status s, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+#define HIP_TRY(call)                                                                      \
+  do {                                                                                     \
+    hipError_t e_ = (call);                                                                \
+    if (e_ != hipSuccess) {                                                                \
+      if (e_ == hipErrorOutOfMemory) return fail(HLB_ENOMEM, "%s: %s", #call, hipGetErrorString(e_)); \
+      return fail(HLB_EDEVICE, "%s: %s", #call, hipGetErrorString(e_));                    \
+    }                                                                                      \
+  } while (0)
+
+constexpr int Q = 19;
+// Velocity set of the input convention (hlb.h), host copy for table building.
+constexpr int CX[Q] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+constexpr int CY[Q] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+constexpr int CZ[Q] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+inline int OPP(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
+inline double W(int i) { return i == 0 ? 1.0 / 3.0 : (i <= 6 ? 1.0 / 18.0 : 1.0 / 36.0); }
+
+size_t storage_bytes(int storage) {
+  return storage == HLB_F64 ? 8 : (storage == HLB_F32_SHIFTED ? 4 : 2);
+}
+
+// group of a site type: bulk and wall are merged (Sec. 3.2.2)
+inline int group_of(int type) {
+  switch (type) {
+    case HLB_SITE_BULK:
+    case HLB_SITE_WALL: return 0;
+    case HLB_SITE_INLET: return 1;
+    case HLB_SITE_OUTLET: return 2;
+    case HLB_SITE_INLET_WALL: return 3;
+    case HLB_SITE_OUTLET_WALL: return 4;
+    default: return -1;
+  }
+}
+
+inline uint64_t spread3(uint64_t v) {
+  v &= 0x1fffffull;
+  v = (v | v << 32) & 0x1f00000000ffffull;
+  v = (v | v << 16) & 0x1f0000ff0000ffull;
+  v = (v | v << 8) & 0x100f00f00f00f00full;
+  v = (v | v << 4) & 0x10c30c30c30c30c3ull;
+  v = (v | v << 2) & 0x1249249249249249ull;
+  return v;
+}
+inline uint64_t morton(uint64_t x, uint64_t y, uint64_t z) { return spread3(x) | spread3(y) << 1 | spread3(z) << 2; }
+
+uint64_t sfc_key(int order, int64_t id, const int32_t *c) {
+  const uint64_t x = (uint64_t)c[0], y = (uint64_t)c[1], z = (uint64_t)c[2];
+  switch (order) {
+    case HLB_ORDER_LEX: return z << 40 | y << 20 | x;
+    case HLB_ORDER_MORTON: return morton(x, y, z);
+    case HLB_ORDER_BRICK: return morton(x >> 2, y >> 2, z >> 2) << 6 | (z & 3) << 4 | (y & 3) << 2 | (x & 3);
+    default: return (uint64_t)id;
+  }
+}
+
+using KeyId = std::pair<uint64_t, int32_t>;
+
+void psort(std::vector<KeyId> &v) {
+  const size_t n = v.size();
+  const int T = omp_get_max_threads();
+  if (n < (1u << 16) || T == 1) {
+    std::sort(v.begin(), v.end());
+    return;
+  }
+  std::vector<size_t> cut(T + 1);
+  for (int t = 0; t <= T; ++t) cut[t] = n * (size_t)t / (size_t)T;
+#pragma omp parallel for schedule(static, 1)
+  for (int t = 0; t < T; ++t) std::sort(v.begin() + cut[t], v.begin() + cut[t + 1]);
+  for (int w = 1; w < T; w *= 2) {
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int t = 0; t < T; t += 2 * w) {
+      if (t + w < T) std::inplace_merge(v.begin() + cut[t], v.begin() + cut[t + w], v.begin() + cut[std::min(t + 2 * w, T)]);
+    }
+  }
+}
+
+struct TimedStep {
+  hipEvent_t e[3];
+};
+
+}  // namespace
+
+struct hlb_ctx {
+  Layout L;
+  DevPtrs d;
+  LaunchCfg cfg;
+  int device = 0;
+  hipStream_t own_stream = nullptr;
+  hipStream_t stream = nullptr;
+  int cur = 0;          // buffer holding the post-collision state of time t
+  bool direct = true;   // other buffer holds the pre-collision state of t
+  int64_t t = 0;
+  int64_t t0 = 0;       // last (re)initialisation
+  double m0 = 0.0;      // mass at t0
+  int order = HLB_ORDER_BRICK;
+  int64_t max_bytes = 0;
+  int64_t dev_bytes = 0;
+  int64_t staging_len = 0;             // doubles in d.io_scratch
+  std::vector<int32_t> order_host;     // [np] caller id per position
+  std::vector<hlb_iolet> iolets;
+  std::vector<std::vector<double>> tables;
+  // timing
+  bool timing = false;
+  std::vector<TimedStep> pool;
+  size_t n_timed = 0;
+  int64_t steps_timed = 0;
+  double sum_bulk = 0, sum_io = 0, sum_step = 0;
+  // snapshots
+  struct Snap {
+    void *f[2] = {nullptr, nullptr};
+    double *acc = nullptr;
+    int64_t t = 0, t0 = 0;
+    double m0 = 0;
+    int cur = 0;
+    bool direct = true;
+    bool valid = false;
+  };
+  std::vector<Snap> snaps;
+};
+
+namespace {
+
+size_t buf_bytes(const hlb_ctx *c) { return (size_t)Q * (size_t)c->L.np * storage_bytes(c->cfg.storage); }
+
+hlb_status dev_alloc(hlb_ctx *c, void **p, size_t bytes) {
+  if (c->max_bytes > 0 && c->dev_bytes + (int64_t)bytes > c->max_bytes)
+    return fail(HLB_ENOMEM, "device budget of %lld bytes exceeded (need %lld more)", (long long)c->max_bytes,
+                (long long)bytes);
+  hipError_t e = hipMalloc(p, bytes ? bytes : 1);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    (void)hipGetLastError();
+    return fail(HLB_ENOMEM, "hipMalloc(%zu bytes): %s", bytes, hipGetErrorString(e));
+  }
+  c->dev_bytes += (int64_t)bytes;
+  return HLB_OK;
+}
+
+void free_all(hlb_ctx *c) {
+  auto F = [](void *p) { if (p) (void)hipFree(p); };
+  F(c->d.f[0]); F(c->d.f[1]); F(c->d.nbr); F(c->d.order); F(c->d.corr); F(c->d.io); F(c->d.tables);
+  F(c->d.phi); F(c->d.acc); F(c->d.partial); F(c->d.io_scratch);
+  for (auto &s : c->snaps) { F(s.f[0]); F(s.f[1]); F(s.acc); }
+  c->snaps.clear();
+  for (auto &ts : c->pool)
+    for (auto &e : ts.e) (void)hipEventDestroy(e);
+  c->pool.clear();
+  if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
+  c->d = DevPtrs();
+}
+
+hlb_status upload_tables(hlb_ctx *c) {
+  const int K = (int)c->iolets.size();
+  if (K == 0) return HLB_OK;
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  std::vector<IoletDev> io(K);
+  std::vector<double> all;
+  for (int k = 0; k < K; ++k) {
+    io[k].kind = c->iolets[k].kind;
+    io[k].tab_len = (int32_t)c->tables[k].size();
+    io[k].tab_off = (int64_t)all.size();
+    for (int a = 0; a < 3; ++a) io[k].n[a] = c->iolets[k].normal[a];
+    io[k].pad = 0.0;
+    all.insert(all.end(), c->tables[k].begin(), c->tables[k].end());
+  }
+  if (c->d.tables) {
+    (void)hipFree(c->d.tables);
+    c->d.tables = nullptr;
+  }
+  void *p = nullptr;
+  hlb_status st = dev_alloc(c, &p, all.size() * sizeof(double));
+  if (st) return st;
+  c->d.tables = static_cast<double *>(p);
+  HIP_TRY(hipMemcpy(c->d.tables, all.data(), all.size() * sizeof(double), hipMemcpyHostToDevice));
+  if (!c->d.io) {
+    st = dev_alloc(c, &p, K * sizeof(IoletDev));
+    if (st) return st;
+    c->d.io = static_cast<IoletDev *>(p);
+  }
+  HIP_TRY(hipMemcpy(c->d.io, io.data(), K * sizeof(IoletDev), hipMemcpyHostToDevice));
+  return HLB_OK;
+}
+
+// Mass of the stored zero: N rho0 for the shifted forms (sum_i w_i = 1),
+// 0 for FP64, which stores f itself.
+double mass_offset(const hlb_ctx *c) {
+  return c->cfg.storage == HLB_F64 ? 0.0 : (double)c->L.n_sites * c->cfg.rho0;
+}
+
+hlb_status check_ctx(const hlb_ctx *c) {
+  if (!c) return fail(HLB_EINVAL, "null context");
+  return HLB_OK;
+}
+
+hlb_status bind(hlb_ctx *c) {
+  HIP_TRY(hipSetDevice(c->device));
+  return HLB_OK;
+}
+
+hlb_status compute_mass(hlb_ctx *c, double *sum_g) {
+  HIP_TRY(launch_mass(c->cfg, c->L, c->d, c->cur, c->stream));
+  HIP_TRY(hipMemcpyAsync(sum_g, c->d.partial, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return HLB_OK;
+}
+
+hlb_status reset_balance(hlb_ctx *c) {
+  HIP_TRY(launch_zero(c->d.acc, 4, c->stream));
+  double s = 0;
+  hlb_status st = compute_mass(c, &s);
+  if (st) return st;
+  c->m0 = mass_offset(c) + s;
+  c->t0 = c->t;
+  return HLB_OK;
+}
+
+// Device staging for host exchanges, grown to `doubles` on demand.
+hlb_status ensure_staging(hlb_ctx *c, int64_t doubles) {
+  if (c->staging_len >= doubles) return HLB_OK;
+  if (c->d.io_scratch) {
+    (void)hipFree(c->d.io_scratch);
+    c->dev_bytes -= c->staging_len * (int64_t)sizeof(double);
+    c->d.io_scratch = nullptr;
+    c->staging_len = 0;
+  }
+  void *p = nullptr;
+  hlb_status st = dev_alloc(c, &p, (size_t)doubles * sizeof(double));
+  if (st) return st;
+  c->d.io_scratch = static_cast<double *>(p);
+  c->staging_len = doubles;
+  return HLB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *hlb_last_error(void) { return g_err.c_str(); }
+
+hlb_status hlb_default_options(hlb_options *opt) {
+  if (!opt) return fail(HLB_EINVAL, "null options");
+  opt->storage = HLB_F64;
+  opt->order = HLB_ORDER_BRICK;
+  opt->xcd_remap = 1;
+  opt->reserved = 0;
+  opt->rho0 = 1.0;
+  opt->max_device_bytes = 0;
+  return HLB_OK;
+}
+
+hlb_status hlb_create(int64_t n, const int32_t *coords, const uint8_t *type, const int32_t *nbr, double tau,
+                      const hlb_iolet *iolets, int32_t n_iolets, const hlb_options *opt_in, hlb_ctx **out) {
+  g_err.clear();
+  if (!out) return fail(HLB_EINVAL, "out is null");
+  *out = nullptr;
+  if (!coords || !type || !nbr) return fail(HLB_EINVAL, "coords, site_type and nbr must be non-null");
+  if (n < 1 || n >= (int64_t)2147483647 - 4096) return fail(HLB_EINVAL, "n_sites=%lld out of range", (long long)n);
+  if (!(tau > 0.5) || !std::isfinite(tau)) return fail(HLB_EINVAL, "tau=%g must be finite and > 1/2", tau);
+  if (n_iolets < 0 || (n_iolets > 0 && !iolets)) return fail(HLB_EINVAL, "bad iolet list");
+  hlb_options opt;
+  hlb_default_options(&opt);
+  if (opt_in) opt = *opt_in;
+  if (opt.storage < HLB_F64 || opt.storage > HLB_F16_SHIFTED) return fail(HLB_EINVAL, "bad storage %d", opt.storage);
+  if (opt.order < HLB_ORDER_INPUT || opt.order > HLB_ORDER_BRICK) return fail(HLB_EINVAL, "bad order %d", opt.order);
+  if (!(opt.rho0 > 0.0) || !std::isfinite(opt.rho0)) return fail(HLB_EINVAL, "rho0 must be finite and > 0");
+  if (opt.reserved != 0 || opt.max_device_bytes < 0) return fail(HLB_EINVAL, "bad options");
+  for (int k = 0; k < n_iolets; ++k) {
+    const hlb_iolet &I = iolets[k];
+    if (I.kind != HLB_IOLET_VELOCITY && I.kind != HLB_IOLET_PRESSURE) return fail(HLB_EINVAL, "iolet %d: bad kind", k);
+    if (I.role != HLB_ROLE_INLET && I.role != HLB_ROLE_OUTLET) return fail(HLB_EINVAL, "iolet %d: bad role", k);
+    const double nn = std::sqrt(I.normal[0] * I.normal[0] + I.normal[1] * I.normal[1] + I.normal[2] * I.normal[2]);
+    if (!(std::fabs(nn - 1.0) < 1e-6)) return fail(HLB_EINVAL, "iolet %d: normal is not a unit vector", k);
+    for (int a = 0; a < 3; ++a)
+      if (!std::isfinite(I.centre[a]) || !std::isfinite(I.vdir[a])) return fail(HLB_EINVAL, "iolet %d: non-finite", k);
+    if (!std::isfinite(I.radius)) return fail(HLB_EINVAL, "iolet %d: non-finite radius", k);
+  }
+
+  // ---- validation of the tables (first offending site reported) ----
+  int64_t bad_site = INT64_MAX;
+  int bad_kind = 0;
+#pragma omp parallel for schedule(static) reduction(min : bad_site)
+  for (int64_t x = 0; x < n; ++x) {
+    const int32_t *row = nbr + Q * x;
+    bool ok = row[0] == x;
+    bool wall = false;
+    int roles = 0;
+    for (int a = 0; a < 3 && ok; ++a) ok = coords[3 * x + a] >= 0 && coords[3 * x + a] < (1 << 20);
+    for (int i = 1; i < Q && ok; ++i) {
+      const int32_t y = row[i];
+      if (y >= 0) {
+        ok = y < n && nbr[Q * (int64_t)y + OPP(i)] == x;
+      } else if (y == HLB_LINK_WALL) {
+        wall = true;
+      } else {
+        const int32_t k = -(y + 2);
+        ok = k >= 0 && k < n_iolets;
+        if (ok) roles |= iolets[k].role == HLB_ROLE_INLET ? 1 : 2;
+      }
+    }
+    if (ok) {
+      int want;
+      if (roles == 3) want = -1;
+      else if (roles == 1) want = wall ? HLB_SITE_INLET_WALL : HLB_SITE_INLET;
+      else if (roles == 2) want = wall ? HLB_SITE_OUTLET_WALL : HLB_SITE_OUTLET;
+      else want = wall ? HLB_SITE_WALL : HLB_SITE_BULK;
+      ok = (int)type[x] == want;
+    }
+    if (!ok && x < bad_site) bad_site = x;
+  }
+  if (bad_site != INT64_MAX) {
+    const int64_t x = bad_site;
+    const int32_t *row = nbr + Q * x;
+    (void)bad_kind;
+    if (row[0] != x) return fail(HLB_EINVAL, "site %lld: nbr[x][0] must be x", (long long)x);
+    for (int a = 0; a < 3; ++a)
+      if (coords[3 * x + a] < 0 || coords[3 * x + a] >= (1 << 20))
+        return fail(HLB_EINVAL, "site %lld: coordinate out of [0, 2^20)", (long long)x);
+    for (int i = 1; i < Q; ++i) {
+      const int32_t y = row[i];
+      if (y >= n) return fail(HLB_EINVAL, "site %lld link %d: neighbour id %d out of range", (long long)x, i, y);
+      if (y >= 0 && nbr[Q * (int64_t)y + OPP(i)] != x)
+        return fail(HLB_EINVAL, "site %lld link %d: neighbour table not symmetric", (long long)x, i);
+      if (y < HLB_LINK_WALL && -(y + 2) >= n_iolets)
+        return fail(HLB_EINVAL, "site %lld link %d: iolet id %d out of range", (long long)x, i, -(y + 2));
+    }
+    return fail(HLB_EINVAL, "site %lld: site type %d disagrees with its link codes", (long long)x, (int)type[x]);
+  }
+
+  hlb_ctx *c = new (std::nothrow) hlb_ctx();
+  if (!c) return fail(HLB_ENOMEM, "host allocation");
+  c->cfg.storage = opt.storage;
+  c->cfg.tau = tau;
+  c->cfg.rho0 = opt.rho0;
+  c->cfg.xcd_remap = opt.xcd_remap != 0;
+  c->cfg.porous = false;
+  c->order = opt.order;
+  c->max_bytes = opt.max_device_bytes;
+  c->iolets.assign(iolets, iolets + n_iolets);
+  c->tables.resize(n_iolets);
+  for (int k = 0; k < n_iolets; ++k)
+    c->tables[k] = {iolets[k].kind == HLB_IOLET_VELOCITY ? 0.0 : opt.rho0};
+
+  // ---- grouping and space-filling-curve order within each group ----
+  Layout &L = c->L;
+  L.n_sites = n;
+  std::vector<std::vector<KeyId>> grp(kGroups);
+  {
+    std::vector<int64_t> cnt(kGroups, 0);
+    for (int64_t x = 0; x < n; ++x) cnt[group_of(type[x])]++;
+    for (int g = 0; g < kGroups; ++g) grp[g].resize(cnt[g]);
+    std::vector<int64_t> fill(kGroups, 0);
+    for (int64_t x = 0; x < n; ++x) {
+      const int g = group_of(type[x]);
+      grp[g][fill[g]++] = KeyId(0, (int32_t)x);
+    }
+    for (int g = 0; g < kGroups; ++g) {
+      auto &v = grp[g];
+#pragma omp parallel for schedule(static)
+      for (int64_t k = 0; k < (int64_t)v.size(); ++k) v[k].first = sfc_key(opt.order, v[k].second, coords + 3 * (int64_t)v[k].second);
+      psort(v);
+    }
+  }
+  int64_t pos = 0;
+  for (int g = 0; g < kGroups; ++g) {
+    L.gbeg[g] = pos;
+    L.gcnt[g] = (int64_t)grp[g].size();
+    pos += L.gcnt[g];
+    pos = (pos + kGroupAlign - 1) / kGroupAlign * kGroupAlign;
+  }
+  L.gbeg[kGroups] = pos;
+  L.np = std::max<int64_t>(pos, kGroupAlign);
+  L.io_begin = L.gbeg[1];
+  L.nio = L.np - L.io_begin;
+  const int64_t np = L.np;
+  c->order_host.assign(np, -1);
+  std::vector<int32_t> inv(n);
+  for (int g = 0; g < kGroups; ++g)
+    for (int64_t k = 0; k < L.gcnt[g]; ++k) {
+      const int32_t x = grp[g][k].second;
+      c->order_host[L.gbeg[g] + k] = x;
+      inv[x] = (int32_t)(L.gbeg[g] + k);
+    }
+  grp.clear();
+  grp.shrink_to_fit();
+
+  // ---- pull table: population i of position p comes from the site at x - c_i ----
+  std::vector<int32_t> pull((size_t)18 * np, HLB_LINK_WALL);
+#pragma omp parallel for schedule(static)
+  for (int64_t p = 0; p < np; ++p) {
+    const int32_t x = c->order_host[p];
+    if (x < 0) continue;
+    for (int i = 1; i < Q; ++i) {
+      const int32_t y = nbr[Q * (int64_t)x + OPP(i)];
+      pull[(size_t)(i - 1) * np + p] = y >= 0 ? inv[y] : y;
+    }
+  }
+  // ---- Ladd coefficients 6 w_i rho0 (c_i . v_k) W_k(x - c_i/2) of velocity-iolet links ----
+  std::vector<double> corr((size_t)18 * L.nio, 0.0);
+#pragma omp parallel for schedule(static)
+  for (int64_t q = 0; q < L.nio; ++q) {
+    const int32_t x = c->order_host[L.io_begin + q];
+    if (x < 0) continue;
+    for (int i = 1; i < Q; ++i) {
+      const int32_t y = nbr[Q * (int64_t)x + OPP(i)];
+      if (y > HLB_LINK_IOLET(0)) continue;
+      const hlb_iolet &I = iolets[-(y + 2)];
+      if (I.kind != HLB_IOLET_VELOCITY) continue;
+      const double m[3] = {coords[3 * (int64_t)x] - 0.5 * CX[i], coords[3 * (int64_t)x + 1] - 0.5 * CY[i],
+                           coords[3 * (int64_t)x + 2] - 0.5 * CZ[i]};
+      double wgt = 1.0;
+      if (I.radius > 0.0) {
+        const double r[3] = {m[0] - I.centre[0], m[1] - I.centre[1], m[2] - I.centre[2]};
+        const double along = r[0] * I.normal[0] + r[1] * I.normal[1] + r[2] * I.normal[2];
+        const double d2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2] - along * along;
+        wgt = std::max(0.0, 1.0 - d2 / (I.radius * I.radius));
+      }
+      const double *v = (I.vdir[0] == 0.0 && I.vdir[1] == 0.0 && I.vdir[2] == 0.0) ? I.normal : I.vdir;
+      const double cv = CX[i] * v[0] + CY[i] * v[1] + CZ[i] * v[2];
+      corr[(size_t)(i - 1) * L.nio + q] = 6.0 * W(i) * opt.rho0 * cv * wgt;
+    }
+  }
+
+  // ---- device set-up (Sec. 3.2.1) ----
+  auto bail = [&](hlb_status st) {
+    std::string msg = g_err;
+    free_all(c);
+    delete c;
+    g_err = msg;
+    return st;
+  };
+  hipError_t he = hipGetDevice(&c->device);
+  if (he != hipSuccess) {
+    (void)hipGetLastError();
+    delete c;
+    return fail(HLB_EDEVICE, "no HIP device: %s", hipGetErrorString(he));
+  }
+  const size_t fb = (size_t)Q * np * storage_bytes(opt.storage);
+  const int64_t partial_len = 1 + 8192;
+  const size_t need = 2 * fb + 18 * np * sizeof(int32_t) + np * sizeof(int32_t) + corr.size() * sizeof(double) +
+                      partial_len * sizeof(double);
+  if (c->max_bytes > 0 && (int64_t)need > c->max_bytes) {
+    delete c;
+    return fail(HLB_ENOMEM, "needs %zu device bytes, budget is %lld", need, (long long)opt.max_device_bytes);
+  }
+  size_t free_b = 0, total_b = 0;
+  if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && need > free_b) {
+    delete c;
+    return fail(HLB_ENOMEM, "needs %zu device bytes, %zu free", need, free_b);
+  }
+  if (hipStreamCreate(&c->own_stream) != hipSuccess) {
+    (void)hipGetLastError();
+    delete c;
+    return fail(HLB_EDEVICE, "hipStreamCreate failed");
+  }
+  c->stream = c->own_stream;
+  void *p = nullptr;
+  hlb_status st;
+  if ((st = dev_alloc(c, &c->d.f[0], fb))) return bail(st);
+  if ((st = dev_alloc(c, &c->d.f[1], fb))) return bail(st);
+  if ((st = dev_alloc(c, &p, 18 * np * sizeof(int32_t)))) return bail(st);
+  c->d.nbr = static_cast<int32_t *>(p);
+  if ((st = dev_alloc(c, &p, np * sizeof(int32_t)))) return bail(st);
+  c->d.order = static_cast<int32_t *>(p);
+  if ((st = dev_alloc(c, &p, std::max<size_t>(1, corr.size()) * sizeof(double)))) return bail(st);
+  c->d.corr = static_cast<double *>(p);
+  if ((st = dev_alloc(c, &p, 4 * sizeof(double)))) return bail(st);
+  c->d.acc = static_cast<double *>(p);
+  if ((st = dev_alloc(c, &p, partial_len * sizeof(double)))) return bail(st);
+  c->d.partial = static_cast<double *>(p);
+  c->d.partial_len = partial_len;
+  auto cp = [&](void *dst, const void *src, size_t bytes) -> hlb_status {
+    hipError_t e = hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return fail(HLB_EDEVICE, "hipMemcpy: %s", hipGetErrorString(e));
+    return HLB_OK;
+  };
+  if ((st = cp(c->d.nbr, pull.data(), pull.size() * sizeof(int32_t)))) return bail(st);
+  if ((st = cp(c->d.order, c->order_host.data(), np * sizeof(int32_t)))) return bail(st);
+  if (!corr.empty() && (st = cp(c->d.corr, corr.data(), corr.size() * sizeof(double)))) return bail(st);
+  if ((st = upload_tables(c))) return bail(st);
+  pull.clear();
+  pull.shrink_to_fit();
+  if ((st = hlb_init_equilibrium(c, nullptr, nullptr, 0))) return bail(st);
+  *out = c;
+  return HLB_OK;
+}
+
+hlb_status hlb_destroy(hlb_ctx *c) {
+  if (!c) return HLB_OK;
+  (void)hipSetDevice(c->device);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  free_all(c);
+  delete c;
+  return HLB_OK;
+}
+
+hlb_status hlb_set_stream(hlb_ctx *c, void *s) {
+  if (hlb_status st = check_ctx(c)) return st;
+  if (hlb_status st = bind(c)) return st;
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  c->stream = s ? static_cast<hipStream_t>(s) : c->own_stream;
+  return HLB_OK;
+}
+
+hlb_status hlb_set_iolet_table(hlb_ctx *c, int32_t k, const double *v, int64_t len) {
+  if (hlb_status st = check_ctx(c)) return st;
+  if (k < 0 || k >= (int32_t)c->iolets.size()) return fail(HLB_EINVAL, "iolet %d out of range", k);
+  if (!v || len < 1 || len > (1ll << 31)) return fail(HLB_EINVAL, "table must have 1..2^31 values");
+  for (int64_t s = 0; s < len; ++s)
+    if (!std::isfinite(v[s])) return fail(HLB_EINVAL, "table value %lld not finite", (long long)s);
+  if (c->iolets[k].kind == HLB_IOLET_PRESSURE)
+    for (int64_t s = 0; s < len; ++s)
+      if (!(v[s] > 0.0)) return fail(HLB_EINVAL, "ghost density must be > 0");
+  if (hlb_status st = bind(c)) return st;
+  c->tables[k].assign(v, v + len);
+  return upload_tables(c);
+}
+
+hlb_status hlb_set_porosity(hlb_ctx *c, const double *phi) {
+  if (hlb_status st = check_ctx(c)) return st;
+  if (hlb_status st = bind(c)) return st;
+  if (!phi) {
+    c->cfg.porous = false;
+    return HLB_OK;
+  }
+  const int64_t n = c->L.n_sites, np = c->L.np;
+  for (int64_t x = 0; x < n; ++x)
+    if (!(phi[x] >= 0.0 && phi[x] <= 1.0)) return fail(HLB_EINVAL, "phi[%lld] not in [0,1]", (long long)x);
+  std::vector<double> h(np, 0.0);
+  for (int64_t p = 0; p < np; ++p)
+    if (c->order_host[p] >= 0) h[p] = phi[c->order_host[p]];
+  if (!c->d.phi) {
+    void *p = nullptr;
+    if (hlb_status st = dev_alloc(c, &p, np * sizeof(double))) return st;
+    c->d.phi = static_cast<double *>(p);
+  }
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  HIP_TRY(hipMemcpy(c->d.phi, h.data(), np * sizeof(double), hipMemcpyHostToDevice));
+  c->cfg.porous = true;
+  return HLB_OK;
+}
+
+hlb_status hlb_init_equilibrium(hlb_ctx *c, const double *rho, const double *u, int64_t t0) {
+  if (hlb_status st = check_ctx(c)) return st;
+  if (t0 < 0) return fail(HLB_EINVAL, "t0 < 0");
+  if (hlb_status st = bind(c)) return st;
+  const int64_t n = c->L.n_sites;
+  const double *staging = nullptr;
+  if (rho || u) {
+    std::vector<double> h((size_t)n * 4);
+    for (int64_t x = 0; x < n; ++x) {
+      h[4 * x] = rho ? rho[x] : c->cfg.rho0;
+      for (int a = 0; a < 3; ++a) h[4 * x + 1 + a] = u ? u[3 * x + a] : 0.0;
+      if (!(h[4 * x] > 0.0) || !std::isfinite(h[4 * x + 1]) || !std::isfinite(h[4 * x + 2]) || !std::isfinite(h[4 * x + 3]))
+        return fail(HLB_EINVAL, "bad initial rho/u at site %lld", (long long)x);
+    }
+    if (hlb_status st = ensure_staging(c, 4 * n)) return st;
+    HIP_TRY(hipMemcpyAsync(c->d.io_scratch, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    staging = c->d.io_scratch;
+    HIP_TRY(launch_init_eq(c->cfg, c->L, c->d, staging, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+  } else {
+    HIP_TRY(launch_init_eq(c->cfg, c->L, c->d, nullptr, c->stream));
+  }
+  c->cur = 0;
+  c->direct = true;
+  c->t = t0;
+  return reset_balance(c);
+}
+
+hlb_status hlb_step(hlb_ctx *c, int64_t n) {
+  if (hlb_status st = check_ctx(c)) return st;
+  if (n < 0) return fail(HLB_EINVAL, "n < 0");
+  if (hlb_status st = bind(c)) return st;
+  for (int64_t s = 0; s < n; ++s) {
+    hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr;
+    if (c->timing) {
+      if (c->n_timed == c->pool.size()) {
+        TimedStep ts;
+        for (auto &e : ts.e) HIP_TRY(hipEventCreate(&e));
+        c->pool.push_back(ts);
+      }
+      TimedStep &ts = c->pool[c->n_timed++];
+      e0 = ts.e[0];
+      e1 = ts.e[1];
+      e2 = ts.e[2];
+    }
+    HIP_TRY(launch_step(c->cfg, c->L, c->d, c->cur, c->t, c->stream, e0, e1, e2));
+    c->cur = 1 - c->cur;
+    c->direct = false;
+    c->t += 1;
+  }
+  return HLB_OK;
+}
+
+hlb_status hlb_macros_device(hlb_ctx *c, void *rho, void *u, void *wss) {
+  if (hlb_status st = check_ctx(c)) return st;
+  if (hlb_status st = bind(c)) return st;
+  if (!rho && !u && !wss) return HLB_OK;
+  HIP_TRY(launch_macros(c->cfg, c->L, c->d, 1 - c->cur, c->direct, c->t - 1, static_cast<double *>(rho),
+                        static_cast<double *>(u), static_cast<double *>(wss), nullptr, c->stream));
+  return HLB_OK;
+}
+
+hlb_status hlb_macros(hlb_ctx *c, double *rho, double *u, double *wss) {
+  if (hlb_status st = check_ctx(c)) return st;
+  if (hlb_status st = bind(c)) return st;
+  if (!rho && !u && !wss) return HLB_OK;
+  const int64_t n = c->L.n_sites;
+  if (hlb_status st = ensure_staging(c, 5 * n)) return st;
+  double *dr = c->d.io_scratch, *du = dr + n, *dw = du + 3 * n;
+  HIP_TRY(launch_macros(c->cfg, c->L, c->d, 1 - c->cur, c->direct, c->t - 1, rho ? dr : nullptr, u ? du : nullptr,
+                        wss ? dw : nullptr, nullptr, c->stream));
+  if (rho) HIP_TRY(hipMemcpyAsync(rho, dr, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  if (u) HIP_TRY(hipMemcpyAsync(u, du, 3 * n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  if (wss) HIP_TRY(hipMemcpyAsync(wss, dw, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  if (rho)
+    for (int64_t x = 0; x < n; ++x)
+      if (!std::isfinite(rho[x])) return fail(HLB_ENUMERIC, "non-finite density at site %lld", (long long)x);
+  return HLB_OK;
+}
+
+hlb_status hlb_get_state(hlb_ctx *c, double *f) {
+  if (hlb_status st = check_ctx(c)) return st;
+  if (!f) return fail(HLB_EINVAL, "f is null");
+  if (hlb_status st = bind(c)) return st;
+  if (hlb_status st = ensure_staging(c, Q * c->L.n_sites)) return st;
+  HIP_TRY(launch_macros(c->cfg, c->L, c->d, 1 - c->cur, c->direct, c->t - 1, nullptr, nullptr, nullptr,
+                        c->d.io_scratch, c->stream));
+  HIP_TRY(hipMemcpyAsync(f, c->d.io_scratch, (size_t)c->L.n_sites * Q * sizeof(double), hipMemcpyDeviceToHost,
+                         c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return HLB_OK;
+}
+
+hlb_status hlb_set_state(hlb_ctx *c, const double *f, int64_t t) {
+  if (hlb_status st = check_ctx(c)) return st;
+  if (!f) return fail(HLB_EINVAL, "f is null");
+  if (t < 0) return fail(HLB_EINVAL, "t < 0");
+  const int64_t n = c->L.n_sites;
+  for (int64_t k = 0; k < n * Q; ++k)
+    if (!std::isfinite(f[k])) return fail(HLB_EINVAL, "f[%lld] not finite", (long long)k);
+  if (hlb_status st = bind(c)) return st;
+  if (hlb_status st = ensure_staging(c, Q * n)) return st;
+  HIP_TRY(hipMemcpyAsync(c->d.io_scratch, f, (size_t)n * Q * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  // buffer 1 := pre-collision f(t), buffer 0 := its collision
+  HIP_TRY(launch_set_state(c->cfg, c->L, c->d, 1, c->d.io_scratch, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  c->cur = 0;
+  c->direct = true;
+  c->t = t;
+  return reset_balance(c);
+}
+
+hlb_status hlb_mass_balance(hlb_ctx *c, double *mass, double *residual) {
+  if (hlb_status st = check_ctx(c)) return st;
+  if (hlb_status st = bind(c)) return st;
+  double s = 0.0, flux = 0.0;
+  if (hlb_status st = compute_mass(c, &s)) return st;
+  HIP_TRY(hipMemcpy(&flux, c->d.acc, sizeof(double), hipMemcpyDeviceToHost));
+  const double M = mass_offset(c) + s;
+  if (mass) *mass = M;
+  if (residual) *residual = M - c->m0 - flux;
+  if (!std::isfinite(M)) return fail(HLB_ENUMERIC, "total mass is not finite");
+  return HLB_OK;
+}
+
+hlb_status hlb_time(const hlb_ctx *c, int64_t *t) {
+  if (!c || !t) return fail(HLB_EINVAL, "null argument");
+  *t = c->t;
+  return HLB_OK;
+}
+
+hlb_status hlb_info(const hlb_ctx *c, hlb_info_t *info) {
+  if (!c || !info) return fail(HLB_EINVAL, "null argument");
+  std::memset(info, 0, sizeof(*info));
+  info->n_sites = c->L.n_sites;
+  info->n_padded = c->L.np;
+  for (int g = 0; g < kGroups; ++g) info->group_sites[g] = c->L.gcnt[g];
+  info->storage = c->cfg.storage;
+  info->order = c->order;
+  // 19 loads + 19 stores of the populations and 18 int32 pull entries per site update
+  info->bytes_per_lup = 38.0 * (double)storage_bytes(c->cfg.storage) + 18.0 * 4.0;
+  info->device_bytes = c->dev_bytes;
+  return HLB_OK;
+}
+
+hlb_status hlb_set_timing(hlb_ctx *c, int32_t enable) {
+  if (hlb_status st = check_ctx(c)) return st;
+  if (hlb_status st = bind(c)) return st;
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  c->timing = enable != 0;
+  c->n_timed = 0;
+  c->steps_timed = 0;
+  c->sum_bulk = c->sum_io = c->sum_step = 0.0;
+  return HLB_OK;
+}
+
+hlb_status hlb_stats(hlb_ctx *c, hlb_stats_t *s) {
+  if (hlb_status st = check_ctx(c)) return st;
+  if (!s) return fail(HLB_EINVAL, "null stats");
+  if (hlb_status st = bind(c)) return st;
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  if (c->n_timed > 0) {
+    for (size_t k = 0; k < c->n_timed; ++k) {
+      float a = 0, b = 0;
+      HIP_TRY(hipEventElapsedTime(&a, c->pool[k].e[0], c->pool[k].e[1]));
+      HIP_TRY(hipEventElapsedTime(&b, c->pool[k].e[1], c->pool[k].e[2]));
+      c->sum_bulk += a;
+      c->sum_io += b;
+    }
+    float whole = 0;
+    HIP_TRY(hipEventElapsedTime(&whole, c->pool[0].e[0], c->pool[c->n_timed - 1].e[2]));
+    c->sum_step += whole;
+    c->steps_timed += (int64_t)c->n_timed;
+    c->n_timed = 0;
+  }
+  s->steps = c->steps_timed;
+  const double k = c->steps_timed > 0 ? (double)c->steps_timed : 1.0;
+  s->bulk_kernel_ms = c->sum_bulk / k;
+  s->iolet_kernel_ms = c->sum_io / k;
+  s->step_ms = c->sum_step / k;
+  return HLB_OK;
+}
+
+hlb_status hlb_snapshot_alloc(hlb_ctx *c, int32_t n_slots) {
+  if (hlb_status st = check_ctx(c)) return st;
+  if (n_slots < 0 || n_slots > 4096) return fail(HLB_EINVAL, "n_slots out of range");
+  if (hlb_status st = bind(c)) return st;
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  for (auto &s : c->snaps) {
+    if (s.f[0]) { (void)hipFree(s.f[0]); c->dev_bytes -= (int64_t)buf_bytes(c); }
+    if (s.f[1]) { (void)hipFree(s.f[1]); c->dev_bytes -= (int64_t)buf_bytes(c); }
+    if (s.acc) { (void)hipFree(s.acc); c->dev_bytes -= 4 * sizeof(double); }
+  }
+  c->snaps.assign(n_slots, hlb_ctx::Snap());
+  for (auto &s : c->snaps) {
+    if (hlb_status st = dev_alloc(c, &s.f[0], buf_bytes(c))) return st;
+    if (hlb_status st = dev_alloc(c, &s.f[1], buf_bytes(c))) return st;
+    void *p = nullptr;
+    if (hlb_status st = dev_alloc(c, &p, 4 * sizeof(double))) return st;
+    s.acc = static_cast<double *>(p);
+  }
+  return HLB_OK;
+}
+
+hlb_status hlb_snapshot_save(hlb_ctx *c, int32_t slot) {
+  if (hlb_status st = check_ctx(c)) return st;
+  if (slot < 0 || slot >= (int32_t)c->snaps.size()) return fail(HLB_EINVAL, "slot %d out of range", slot);
+  if (hlb_status st = bind(c)) return st;
+  auto &s = c->snaps[slot];
+  HIP_TRY(hipMemcpyAsync(s.f[0], c->d.f[0], buf_bytes(c), hipMemcpyDeviceToDevice, c->stream));
+  HIP_TRY(hipMemcpyAsync(s.f[1], c->d.f[1], buf_bytes(c), hipMemcpyDeviceToDevice, c->stream));
+  HIP_TRY(hipMemcpyAsync(s.acc, c->d.acc, 4 * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  s.t = c->t; s.t0 = c->t0; s.m0 = c->m0; s.cur = c->cur; s.direct = c->direct; s.valid = true;
+  return HLB_OK;
+}
+
+hlb_status hlb_snapshot_restore(hlb_ctx *c, int32_t slot) {
+  if (hlb_status st = check_ctx(c)) return st;
+  if (slot < 0 || slot >= (int32_t)c->snaps.size()) return fail(HLB_EINVAL, "slot %d out of range", slot);
+  auto &s = c->snaps[slot];
+  if (!s.valid) return fail(HLB_ESTATE, "slot %d holds no snapshot", slot);
+  if (hlb_status st = bind(c)) return st;
+  HIP_TRY(hipMemcpyAsync(c->d.f[0], s.f[0], buf_bytes(c), hipMemcpyDeviceToDevice, c->stream));
+  HIP_TRY(hipMemcpyAsync(c->d.f[1], s.f[1], buf_bytes(c), hipMemcpyDeviceToDevice, c->stream));
+  HIP_TRY(hipMemcpyAsync(c->d.acc, s.acc, 4 * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  c->t = s.t; c->t0 = s.t0; c->m0 = s.m0; c->cur = s.cur; c->direct = s.direct;
+  return HLB_OK;
+}
+
+namespace {
+struct StateHeader {
+  char magic[8];
+  int64_t n_sites, np, t, t0;
+  int32_t storage, cur, direct, pad;
+  double m0;
+  double acc[4];
+};
+}  // namespace
+
+hlb_status hlb_state_bytes(const hlb_ctx *c, int64_t *bytes) {
+  if (!c || !bytes) return fail(HLB_EINVAL, "null argument");
+  *bytes = (int64_t)(sizeof(StateHeader) + 2 * buf_bytes(c));
+  return HLB_OK;
+}
+
+hlb_status hlb_state_save(hlb_ctx *c, void *buf) {
+  if (hlb_status st = check_ctx(c)) return st;
+  if (!buf) return fail(HLB_EINVAL, "null buffer");
+  if (hlb_status st = bind(c)) return st;
+  StateHeader h;
+  std::memset(&h, 0, sizeof(h));
+  std::memcpy(h.magic, "HLBSTAT1", 8);
+  h.n_sites = c->L.n_sites; h.np = c->L.np; h.t = c->t; h.t0 = c->t0;
+  h.storage = c->cfg.storage; h.cur = c->cur; h.direct = c->direct ? 1 : 0; h.m0 = c->m0;
+  HIP_TRY(hipMemcpyAsync(h.acc, c->d.acc, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  char *b = static_cast<char *>(buf);
+  HIP_TRY(hipMemcpyAsync(b + sizeof(h), c->d.f[0], buf_bytes(c), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipMemcpyAsync(b + sizeof(h) + buf_bytes(c), c->d.f[1], buf_bytes(c), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  std::memcpy(b, &h, sizeof(h));
+  return HLB_OK;
+}
+
+hlb_status hlb_state_load(hlb_ctx *c, const void *buf) {
+  if (hlb_status st = check_ctx(c)) return st;
+  if (!buf) return fail(HLB_EINVAL, "null buffer");
+  StateHeader h;
+  std::memcpy(&h, buf, sizeof(h));
+  if (std::memcmp(h.magic, "HLBSTAT1", 8) != 0 || h.n_sites != c->L.n_sites || h.np != c->L.np ||
+      h.storage != c->cfg.storage)
+    return fail(HLB_EINVAL, "state buffer does not match this context");
+  if (hlb_status st = bind(c)) return st;
+  const char *b = static_cast<const char *>(buf);
+  HIP_TRY(hipMemcpyAsync(c->d.f[0], b + sizeof(h), buf_bytes(c), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipMemcpyAsync(c->d.f[1], b + sizeof(h) + buf_bytes(c), buf_bytes(c), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipMemcpyAsync(c->d.acc, h.acc, 4 * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  c->t = h.t; c->t0 = h.t0; c->m0 = h.m0; c->cur = h.cur; c->direct = h.direct != 0;
+  return HLB_OK;
+}
+
+hlb_status hlb_sync(hlb_ctx *c) {
+  if (hlb_status st = check_ctx(c)) return st;
+  if (hlb_status st = bind(c)) return st;
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return HLB_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,363 @@
+"""Python binding of the C ABI in include/hlb.h (argument marshalling only).
+
+Every function here has the name of the C entry point it calls and does no
+computation of its own: the update, the boundary rules, the macroscopic
+fields and the reductions all run in libhlb.so's gfx950 kernels.  If the
+library has not been built this module raises on first use; there is no
+fallback.
+
+Arrays are numpy (host) or anything exposing a device pointer (an integer,
+or an object with ``data_ptr()`` such as a torch tensor on the GPU).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(_HERE, "libhlb.so")
+
+HLB_OK, HLB_EINVAL, HLB_ENOMEM, HLB_EDEVICE, HLB_ESTATE, HLB_ENUMERIC = 0, -1, -2, -3, -4, -5
+STATUS_NAMES = {0: "HLB_OK", -1: "HLB_EINVAL", -2: "HLB_ENOMEM", -3: "HLB_EDEVICE", -4: "HLB_ESTATE",
+                -5: "HLB_ENUMERIC"}
+HLB_F64, HLB_F32_SHIFTED, HLB_F16_SHIFTED = 0, 1, 2
+STORAGE = {"f64": HLB_F64, "f32": HLB_F32_SHIFTED, "f16": HLB_F16_SHIFTED}
+HLB_ORDER_INPUT, HLB_ORDER_LEX, HLB_ORDER_MORTON, HLB_ORDER_BRICK = 0, 1, 2, 3
+ORDER = {"input": 0, "lex": 1, "morton": 2, "brick": 3}
+Q = 19
+
+
+class HLBError(RuntimeError):
+    def __init__(self, status: int, where: str, message: str):
+        super().__init__(f"{where}: {STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+class hlb_iolet(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("role", ctypes.c_int32), ("centre", ctypes.c_double * 3),
+                ("normal", ctypes.c_double * 3), ("radius", ctypes.c_double), ("vdir", ctypes.c_double * 3)]
+
+
+class hlb_options(ctypes.Structure):
+    _fields_ = [("storage", ctypes.c_int32), ("order", ctypes.c_int32), ("xcd_remap", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("rho0", ctypes.c_double), ("max_device_bytes", ctypes.c_int64)]
+
+
+class hlb_info_t(ctypes.Structure):
+    _fields_ = [("n_sites", ctypes.c_int64), ("n_padded", ctypes.c_int64), ("group_sites", ctypes.c_int64 * 6),
+                ("storage", ctypes.c_int32), ("order", ctypes.c_int32), ("bytes_per_lup", ctypes.c_double),
+                ("device_bytes", ctypes.c_int64)]
+
+
+class hlb_stats_t(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_int64), ("bulk_kernel_ms", ctypes.c_double),
+                ("iolet_kernel_ms", ctypes.c_double), ("step_ms", ctypes.c_double)]
+
+
+_P = ctypes.c_void_p
+_i64 = ctypes.c_int64
+_i32 = ctypes.c_int32
+_d = ctypes.c_double
+_PP = ctypes.POINTER(ctypes.c_void_p)
+
+# name -> argtypes (restype is the int status unless noted)
+_SIGS = {
+    "hlb_default_options": [ctypes.POINTER(hlb_options)],
+    "hlb_create": [_i64, _P, _P, _P, _d, _P, _i32, ctypes.POINTER(hlb_options), _PP],
+    "hlb_destroy": [_P],
+    "hlb_set_stream": [_P, _P],
+    "hlb_set_iolet_table": [_P, _i32, _P, _i64],
+    "hlb_set_porosity": [_P, _P],
+    "hlb_init_equilibrium": [_P, _P, _P, _i64],
+    "hlb_step": [_P, _i64],
+    "hlb_macros": [_P, _P, _P, _P],
+    "hlb_macros_device": [_P, _P, _P, _P],
+    "hlb_get_state": [_P, _P],
+    "hlb_set_state": [_P, _P, _i64],
+    "hlb_mass_balance": [_P, _P, _P],
+    "hlb_time": [_P, ctypes.POINTER(_i64)],
+    "hlb_info": [_P, ctypes.POINTER(hlb_info_t)],
+    "hlb_set_timing": [_P, _i32],
+    "hlb_stats": [_P, ctypes.POINTER(hlb_stats_t)],
+    "hlb_snapshot_alloc": [_P, _i32],
+    "hlb_snapshot_save": [_P, _i32],
+    "hlb_snapshot_restore": [_P, _i32],
+    "hlb_state_bytes": [_P, ctypes.POINTER(_i64)],
+    "hlb_state_save": [_P, _P],
+    "hlb_state_load": [_P, _P],
+    "hlb_sync": [_P],
+    "hlb_last_error": [],
+}
+EXPORTED = tuple(_SIGS)
+
+_lib = None
+
+
+def _bind_torch_runtime():
+    """One HIP runtime per process: torch ships its own libamdhip64.so.7, so
+    load it (by importing torch) before libhlb.so, whose dependency of the same
+    soname then resolves to it.  Device pointers and streams from torch are
+    then valid in the library."""
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        return
+
+
+def load():
+    """Load libhlb.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    _bind_torch_runtime()
+    if not os.path.exists(LIBPATH):
+        raise RuntimeError(f"{LIBPATH} is missing: build it with __graft_entry__.build() "
+                           "(python -m paper_2202_11770_amd.build)")
+    lib = ctypes.CDLL(LIBPATH)
+    for name, args in _SIGS.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    lib.hlb_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def hlb_last_error() -> str:
+    return load().hlb_last_error().decode()
+
+
+def _check(status: int, where: str):
+    if status != HLB_OK:
+        raise HLBError(status, where, hlb_last_error())
+
+
+def _host(a, dtype, shape=None):
+    if a is None:
+        return None, None
+    arr = np.ascontiguousarray(a, dtype=dtype)
+    if shape is not None and arr.shape != shape:
+        arr = arr.reshape(shape)
+    return arr, arr.ctypes.data_as(_P)
+
+
+def _devptr(x):
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return _P(x)
+    return _P(int(x.data_ptr()))
+
+
+def make_iolets(iolets):
+    arr = (hlb_iolet * max(1, len(iolets)))()
+    for k, io in enumerate(iolets):
+        arr[k].kind = int(io.kind)
+        arr[k].role = int(io.role)
+        arr[k].centre[:] = [float(v) for v in io.centre]
+        arr[k].normal[:] = [float(v) for v in io.normal]
+        arr[k].radius = float(io.radius)
+        vd = getattr(io, "vdir", None) or (0.0, 0.0, 0.0)
+        arr[k].vdir[:] = [float(v) for v in vd]
+    return arr
+
+
+def hlb_default_options() -> hlb_options:
+    o = hlb_options()
+    _check(load().hlb_default_options(ctypes.byref(o)), "hlb_default_options")
+    return o
+
+
+def hlb_create(coords, site_type, nbr, tau: float, iolets=(), options: hlb_options | None = None):
+    """Returns an opaque context handle (ctypes.c_void_p)."""
+    c, cp = _host(coords, np.int32)
+    t, tp = _host(site_type, np.uint8)
+    nb, nbp = _host(nbr, np.int32)
+    n = int(t.shape[0])
+    if c.shape != (n, 3) or nb.shape != (n, Q):
+        raise ValueError("coords must be (n,3) and nbr (n,19)")
+    io = make_iolets(list(iolets))
+    out = ctypes.c_void_p()
+    opt = ctypes.byref(options) if options is not None else None
+    _check(load().hlb_create(n, cp, tp, nbp, float(tau), ctypes.cast(io, _P), len(iolets), opt, ctypes.byref(out)),
+           "hlb_create")
+    return out
+
+
+def hlb_destroy(ctx):
+    _check(load().hlb_destroy(ctx), "hlb_destroy")
+
+
+def hlb_set_stream(ctx, stream):
+    """stream: a hipStream_t as an int (e.g. torch.cuda.current_stream().cuda_stream) or None."""
+    _check(load().hlb_set_stream(ctx, _P(int(stream)) if stream else None), "hlb_set_stream")
+
+
+def hlb_set_iolet_table(ctx, k: int, values):
+    v, vp = _host(values, np.float64)
+    v = v.reshape(-1)
+    _check(load().hlb_set_iolet_table(ctx, int(k), vp, v.size), "hlb_set_iolet_table")
+
+
+def hlb_set_porosity(ctx, phi):
+    p, pp = _host(phi, np.float64)
+    _check(load().hlb_set_porosity(ctx, pp), "hlb_set_porosity")
+
+
+def hlb_init_equilibrium(ctx, rho=None, u=None, t0: int = 0):
+    r, rp = _host(rho, np.float64)
+    v, vp = _host(u, np.float64)
+    _check(load().hlb_init_equilibrium(ctx, rp, vp, int(t0)), "hlb_init_equilibrium")
+
+
+def hlb_step(ctx, n: int):
+    _check(load().hlb_step(ctx, int(n)), "hlb_step")
+
+
+def hlb_info(ctx) -> dict:
+    i = hlb_info_t()
+    _check(load().hlb_info(ctx, ctypes.byref(i)), "hlb_info")
+    return dict(n_sites=i.n_sites, n_padded=i.n_padded, group_sites=list(i.group_sites)[:5], storage=i.storage,
+                order=i.order, bytes_per_lup=i.bytes_per_lup, device_bytes=i.device_bytes)
+
+
+def hlb_macros(ctx, want=("rho", "u", "wss")):
+    n = hlb_info(ctx)["n_sites"]
+    rho = np.empty(n) if "rho" in want else None
+    u = np.empty((n, 3)) if "u" in want else None
+    wss = np.empty(n) if "wss" in want else None
+    P = lambda a: a.ctypes.data_as(_P) if a is not None else None
+    _check(load().hlb_macros(ctx, P(rho), P(u), P(wss)), "hlb_macros")
+    return rho, u, wss
+
+
+def hlb_macros_device(ctx, rho=None, u=None, wss=None):
+    _check(load().hlb_macros_device(ctx, _devptr(rho), _devptr(u), _devptr(wss)), "hlb_macros_device")
+
+
+def hlb_get_state(ctx) -> np.ndarray:
+    n = hlb_info(ctx)["n_sites"]
+    f = np.empty((n, Q))
+    _check(load().hlb_get_state(ctx, f.ctypes.data_as(_P)), "hlb_get_state")
+    return f
+
+
+def hlb_set_state(ctx, f, t: int):
+    a, ap = _host(f, np.float64)
+    _check(load().hlb_set_state(ctx, ap, int(t)), "hlb_set_state")
+
+
+def hlb_mass_balance(ctx):
+    m = ctypes.c_double()
+    r = ctypes.c_double()
+    _check(load().hlb_mass_balance(ctx, ctypes.byref(m), ctypes.byref(r)), "hlb_mass_balance")
+    return m.value, r.value
+
+
+def hlb_time(ctx) -> int:
+    t = ctypes.c_int64()
+    _check(load().hlb_time(ctx, ctypes.byref(t)), "hlb_time")
+    return t.value
+
+
+def hlb_set_timing(ctx, enable: bool):
+    _check(load().hlb_set_timing(ctx, 1 if enable else 0), "hlb_set_timing")
+
+
+def hlb_stats(ctx) -> dict:
+    s = hlb_stats_t()
+    _check(load().hlb_stats(ctx, ctypes.byref(s)), "hlb_stats")
+    return dict(steps=s.steps, bulk_kernel_ms=s.bulk_kernel_ms, iolet_kernel_ms=s.iolet_kernel_ms, step_ms=s.step_ms)
+
+
+def hlb_snapshot_alloc(ctx, n_slots: int):
+    _check(load().hlb_snapshot_alloc(ctx, int(n_slots)), "hlb_snapshot_alloc")
+
+
+def hlb_snapshot_save(ctx, slot: int):
+    _check(load().hlb_snapshot_save(ctx, int(slot)), "hlb_snapshot_save")
+
+
+def hlb_snapshot_restore(ctx, slot: int):
+    _check(load().hlb_snapshot_restore(ctx, int(slot)), "hlb_snapshot_restore")
+
+
+def hlb_state_bytes(ctx) -> int:
+    b = ctypes.c_int64()
+    _check(load().hlb_state_bytes(ctx, ctypes.byref(b)), "hlb_state_bytes")
+    return b.value
+
+
+def hlb_state_save(ctx) -> bytearray:
+    buf = bytearray(hlb_state_bytes(ctx))
+    cbuf = (ctypes.c_char * len(buf)).from_buffer(buf)
+    _check(load().hlb_state_save(ctx, ctypes.cast(cbuf, _P)), "hlb_state_save")
+    return buf
+
+
+def hlb_state_load(ctx, buf):
+    b = bytearray(buf)
+    cbuf = (ctypes.c_char * len(b)).from_buffer(b)
+    _check(load().hlb_state_load(ctx, ctypes.cast(cbuf, _P)), "hlb_state_load")
+
+
+def hlb_sync(ctx):
+    _check(load().hlb_sync(ctx), "hlb_sync")
+
+
+# ---------------------------------------------------------------------------
+
+@dataclass
+class Simulation:
+    """Owning wrapper of one context built from a geometry-like object
+    (``coords``, ``types``, ``nbr``, ``iolets`` with optional ``table``)."""
+
+    ctx: ctypes.c_void_p
+    n: int
+
+    @classmethod
+    def create(cls, geom, tau: float, storage: str = "f64", order: str = "brick", xcd_remap: bool = True,
+               rho0: float = 1.0, max_device_bytes: int = 0, tables=None):
+        opt = hlb_default_options()
+        opt.storage = STORAGE[storage]
+        opt.order = ORDER[order]
+        opt.xcd_remap = 1 if xcd_remap else 0
+        opt.rho0 = float(rho0)
+        opt.max_device_bytes = int(max_device_bytes)
+        ctx = hlb_create(geom.coords, geom.types, geom.nbr, tau, geom.iolets, opt)
+        sim = cls(ctx, int(geom.types.shape[0]))
+        for k, io in enumerate(geom.iolets):
+            tab = tables[k] if tables is not None and tables[k] is not None else getattr(io, "table", None)
+            if tab is not None:
+                hlb_set_iolet_table(ctx, k, tab)
+        return sim
+
+    def close(self):
+        if self.ctx:
+            hlb_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, n: int = 1):
+        hlb_step(self.ctx, n)
+
+    def macros(self):
+        return hlb_macros(self.ctx)
+
+    def state(self):
+        return hlb_get_state(self.ctx)
+
+    @property
+    def t(self) -> int:
+        return hlb_time(self.ctx)
+
+    def info(self) -> dict:
+        return hlb_info(self.ctx)

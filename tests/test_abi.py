@@ -1,0 +1,127 @@
+"""C-ABI library: loads, exports every declared symbol, rejects bad inputs.
+
+No compute runs here: every call below fails validation on the host before
+the library touches a device.
+"""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2202_11770_amd import geometry as G
+from paper_2202_11770_amd import hlb
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "hlb.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(hlb_[a-z_]+)\s*\(", txt)) - {"hlb_status"})
+
+
+def test_exports_every_declared_symbol():
+    lib = hlb.load()
+    names = _declared()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(hlb.EXPORTED)
+    out = os.popen(f"nm -D --defined-only {hlb.LIBPATH}").read()
+    for n in names:
+        assert re.search(rf"\bT {n}\b", out), n
+
+
+def test_default_options():
+    o = hlb.hlb_default_options()
+    assert (o.storage, o.order, o.xcd_remap, o.reserved, o.rho0, o.max_device_bytes) == (0, 3, 1, 0, 1.0, 0)
+
+
+@pytest.fixture(scope="module")
+def cyl():
+    return G.cylinder()
+
+
+def _expect(status, fn, *a, match=None):
+    with pytest.raises(hlb.HLBError) as e:
+        fn(*a)
+    assert e.value.status == status
+    if match:
+        assert re.search(match, str(e.value)), str(e.value)
+
+
+def test_rejects_bad_tau(cyl):
+    for tau in (0.5, 0.2, float("nan"), float("inf")):
+        _expect(hlb.HLB_EINVAL, hlb.hlb_create, cyl.coords, cyl.types, cyl.nbr, tau, cyl.iolets, match="tau")
+
+
+def test_rejects_asymmetric_table(cyl):
+    nbr = cyl.nbr.copy()
+    x = 5000
+    i = 1
+    y = nbr[x, i]
+    assert y >= 0
+    nbr[y, 2] = -1  # break the back link
+    _expect(hlb.HLB_EINVAL, hlb.hlb_create, cyl.coords, cyl.types, nbr, 0.8, cyl.iolets, match="symmetric|type")
+
+
+def test_rejects_type_mismatch(cyl):
+    t = cyl.types.copy()
+    x = int(np.nonzero(t == G.SITE_BULK)[0][0])
+    t[x] = G.SITE_WALL
+    _expect(hlb.HLB_EINVAL, hlb.hlb_create, cyl.coords, t, cyl.nbr, 0.8, cyl.iolets, match=f"site {x}: site type")
+
+
+def test_rejects_bad_iolet_id(cyl):
+    nbr = cyl.nbr.copy()
+    x, i = np.argwhere(nbr == -3)[0]
+    nbr[x, i] = -9
+    _expect(hlb.HLB_EINVAL, hlb.hlb_create, cyl.coords, cyl.types, nbr, 0.8, cyl.iolets, match="iolet id")
+
+
+def test_rejects_self_entry(cyl):
+    nbr = cyl.nbr.copy()
+    nbr[3, 0] = 4
+    _expect(hlb.HLB_EINVAL, hlb.hlb_create, cyl.coords, cyl.types, nbr, 0.8, cyl.iolets, match="nbr\\[x\\]\\[0\\]")
+
+
+def test_rejects_neighbour_out_of_range(cyl):
+    nbr = cyl.nbr.copy()
+    nbr[0, 5] = cyl.n + 10
+    _expect(hlb.HLB_EINVAL, hlb.hlb_create, cyl.coords, cyl.types, nbr, 0.8, cyl.iolets, match="out of range")
+
+
+def test_rejects_bad_iolet_descriptor(cyl):
+    import copy
+    ios = copy.deepcopy(cyl.iolets)
+    ios[0].normal = (0.0, 0.0, 2.0)
+    _expect(hlb.HLB_EINVAL, hlb.hlb_create, cyl.coords, cyl.types, cyl.nbr, 0.8, ios, match="unit")
+    ios = copy.deepcopy(cyl.iolets)
+    ios[1].kind = 7
+    _expect(hlb.HLB_EINVAL, hlb.hlb_create, cyl.coords, cyl.types, cyl.nbr, 0.8, ios, match="kind")
+
+
+def test_rejects_bad_options(cyl):
+    o = hlb.hlb_default_options()
+    o.storage = 9
+    _expect(hlb.HLB_EINVAL, hlb.hlb_create, cyl.coords, cyl.types, cyl.nbr, 0.8, cyl.iolets, o)
+    o = hlb.hlb_default_options()
+    o.rho0 = -1.0
+    _expect(hlb.HLB_EINVAL, hlb.hlb_create, cyl.coords, cyl.types, cyl.nbr, 0.8, cyl.iolets, o)
+    o = hlb.hlb_default_options()
+    o.reserved = 1
+    _expect(hlb.HLB_EINVAL, hlb.hlb_create, cyl.coords, cyl.types, cyl.nbr, 0.8, cyl.iolets, o)
+
+
+def test_null_arguments():
+    lib = hlb.load()
+    out = hlb.ctypes.c_void_p()
+    assert lib.hlb_create(10, None, None, None, 0.8, None, 0, None, hlb.ctypes.byref(out)) == hlb.HLB_EINVAL
+    assert "non-null" in hlb.hlb_last_error()
+    assert lib.hlb_create(0, None, None, None, 0.8, None, 0, None, None) == hlb.HLB_EINVAL
+    assert lib.hlb_step(None, 1) == hlb.HLB_EINVAL
+    assert lib.hlb_macros(None, None, None, None) == hlb.HLB_EINVAL
+    assert lib.hlb_mass_balance(None, None, None) == hlb.HLB_EINVAL
+    assert lib.hlb_destroy(None) == hlb.HLB_OK
+    assert lib.hlb_time(None, None) == hlb.HLB_EINVAL

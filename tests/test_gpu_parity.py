@@ -1,0 +1,282 @@
+"""GPU parity: the gfx950 path (through the C ABI) against the FP64 oracle.
+
+Bar (FP64 storage): e_rho, e_u <= 1e-12 and e_wss <= 1e-10 (relative
+metrics of tests/_parity.py); bit-exact where the method leaves no freedom
+(site-order invariance, rest state in the shifted variables, save/load).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2202_11770_amd import geometry as G
+from paper_2202_11770_amd import hlb
+from _parity import errors, fmt
+
+pytestmark = pytest.mark.gpu
+
+TOL_RHO = 1e-12
+TOL_U = 1e-12
+TOL_WSS = 1e-10
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _oracle_run(g, tau, steps, tables=None, phi=None, init=None):
+    P = oracle.Problem(g, tau, tables=tables, phi=phi)
+    f = P.init(*init) if init is not None else P.init()
+    P.run(f, 0, steps)
+    return P, f
+
+
+def _gpu_run(g, tau, steps, storage="f64", order="brick", xcd=True, tables=None, phi=None, init=None):
+    sim = hlb.Simulation.create(g, tau, storage=storage, order=order, xcd_remap=xcd, tables=tables)
+    if phi is not None:
+        hlb.hlb_set_porosity(sim.ctx, phi)
+    if init is not None:
+        hlb.hlb_init_equilibrium(sim.ctx, init[0], init[1], 0)
+    sim.step(steps)
+    return sim
+
+
+def _compare(g, tau, steps, storage="f64", **kw):
+    P, f = _oracle_run(g, tau, steps, kw.get("tables"), kw.get("phi"), kw.get("init"))
+    rho_r, u_r, wss_r = P.macros(f)
+    sim = _gpu_run(g, tau, steps, storage=storage, **kw)
+    rho, u, wss = sim.macros()
+    e = errors(rho, u, wss, rho_r, u_r, wss_r)
+    return e, sim, P, f
+
+
+def test_cylinder_fp64_2000_steps():
+    g = G.cylinder()
+    say("case: cylinder 13312 sites, tau 0.8, 2000 steps, f64")
+    e, sim, P, f = _compare(g, 0.8, 2000)
+    say("cylinder f64:", fmt(e))
+    assert e["e_rho"] <= TOL_RHO and e["e_u"] <= TOL_U and e["e_wss"] <= TOL_WSS
+    # populations of the pre-collision state at t = 2000
+    fg = sim.state()
+    assert np.abs(fg - f).max() <= 1e-13
+    assert sim.t == 2000
+    # mass bookkeeping of the iolets: residual at rounding level
+    m, r = hlb.hlb_mass_balance(sim.ctx)
+    assert abs(m - P.mass(f)) / m <= 1e-12
+    assert abs(r) / m <= 2000 * 19 * 2.0 ** -53 / 0.8
+    sim.close()
+
+
+def _small_tree():
+    return G.tree(seed=3, generations=3, target_sites=30000)
+
+
+def _tree_tables(g, period=200, amp=0.02):
+    s = np.arange(period)
+    tabs = []
+    for k, io in enumerate(g.iolets):
+        if io.kind == G.VELOCITY:
+            tabs.append(amp * 0.5 * (1 - np.cos(2 * np.pi * s / period)))
+        elif k == len(g.iolets) - 1:
+            tabs.append(1.0 + 0.002 * np.sin(2 * np.pi * s / 50.0))  # time-varying ghost density
+        else:
+            tabs.append(np.array([1.0]))
+    return tabs
+
+
+def test_tree_fp64_time_varying_iolets():
+    g = _small_tree()
+    tabs = _tree_tables(g)
+    say(f"case: tree {g.n} sites, {len(g.iolets)} iolets, tau 0.6, 400 steps, f64")
+    e, sim, P, f = _compare(g, 0.6, 400, tables=tabs)
+    say("tree f64:", fmt(e))
+    assert e["e_rho"] <= TOL_RHO and e["e_u"] <= TOL_U and e["e_wss"] <= TOL_WSS
+    fg = sim.state()
+    assert np.abs(fg - f).max() <= 1e-13
+    sim.close()
+
+
+@pytest.mark.parametrize("order,xcd", [("input", True), ("lex", False), ("morton", True), ("brick", False)])
+def test_site_order_is_invisible(order, xcd):
+    """The update of a site reads the same values whatever the internal
+    order, so every order gives bit-identical results."""
+    g = _small_tree()
+    tabs = _tree_tables(g)
+    say(f"case: order {order} xcd {xcd}")
+    ref = _gpu_run(g, 0.6, 150, tables=tabs)
+    a = ref.macros()
+    sim = _gpu_run(g, 0.6, 150, order=order, xcd=xcd, tables=tabs)
+    b = sim.macros()
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+    ref.close()
+    sim.close()
+
+
+def test_caller_permutation_invariance():
+    g = G.cylinder()
+    perm = np.random.default_rng(5).permutation(g.n)
+    gp = G.permute(g, perm)
+    a = _gpu_run(g, 0.8, 200)
+    b = _gpu_run(gp, 0.8, 200)
+    ra, ua, wa = a.macros()
+    rb, ub, wb = b.macros()
+    assert np.array_equal(ra[perm], rb) and np.array_equal(ua[perm], ub) and np.array_equal(wa[perm], wb)
+    a.close()
+    b.close()
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
+def test_rest_state(storage):
+    """At rest with rest-state boundary data the fluid stays at rest.  The
+    shifted forms store exact zeros, so rho == rho0 and f == w bit for bit;
+    FP64 stores f itself, whose weights sum to 1 + 2^-52 in floating point,
+    so it stays within 1e-15 (as the oracle does)."""
+    g = G.cylinder(u_max=0.0, rho_out=1.0)
+    sim = _gpu_run(g, 0.8, 500, storage=storage)
+    rho, u, wss = sim.macros()
+    _, w, _ = oracle.lattice()
+    f = sim.state()
+    if storage == "f64":
+        assert np.abs(rho - 1.0).max() <= 1e-15 and np.abs(u).max() <= 1e-15 and wss.max() <= 1e-16
+        assert np.abs(f - w[None, :]).max() <= 1e-15
+    else:
+        assert np.all(rho == 1.0) and np.all(u == 0.0) and np.all(wss == 0.0)
+        assert np.array_equal(f, np.broadcast_to(w, (g.n, 19)))
+    sim.close()
+
+
+def test_sealed_box_random_init():
+    """Random equilibrium start in a closed bounce-back box.  The flow decays
+    viscously while the GPU-oracle difference stays at the rounding level, so
+    the relative velocity error is taken at t = 150, before the reference
+    velocity has decayed towards that level; mass is checked over 1000 steps."""
+    g = G.sealed_box(20)
+    rng = np.random.default_rng(7)
+    rho0 = 1.0 + rng.uniform(-0.01, 0.01, g.n)
+    u0 = rng.uniform(-1, 1, (g.n, 3))
+    u0 *= (0.02 * rng.uniform(0, 1, g.n) / np.linalg.norm(u0, axis=1))[:, None]
+    e, sim, P, f = _compare(g, 0.6, 150, init=(rho0, u0))
+    _, u_r, _ = P.macros(f)
+    say("sealed box f64 t=150:", fmt(e), f"max|u_ref|={np.linalg.norm(u_r, axis=1).max():.2e}")
+    assert e["e_rho"] <= TOL_RHO and e["e_u"] <= TOL_U and e["e_wss"] <= TOL_WSS
+    P.run(f, 150, 850)
+    sim.step(850)
+    m, r = hlb.hlb_mass_balance(sim.ctx)
+    # closed box: conserved up to the per-collision rounding of the density
+    # sum (the oracle's bound), and equal to the oracle's mass
+    assert abs(r) / m <= 1000 * 19 * 2.0 ** -53 / 0.6
+    assert abs(m - P.mass(f)) / m <= 1e-12
+    sim.close()
+
+
+def test_porous_walls():
+    g = _small_tree()
+    tabs = _tree_tables(g)
+    rng = np.random.default_rng(40)
+    phi = np.zeros(g.n)
+    ws = g.wall_sites()
+    phi[ws] = rng.uniform(0, 1, ws.size)
+    e, sim, P, f = _compare(g, 0.6, 300, tables=tabs, phi=phi)
+    say("porous tree f64:", fmt(e))
+    assert e["e_rho"] <= TOL_RHO and e["e_u"] <= TOL_U and e["e_wss"] <= TOL_WSS
+    m, r = hlb.hlb_mass_balance(sim.ctx)
+    assert abs(m - P.mass(f)) / m <= 1e-12
+    assert abs(r) / m <= 300 * 19 * 2.0 ** -53 / 0.6
+    sim.close()
+
+
+def test_set_state_then_step():
+    g = G.cylinder()
+    P = oracle.Problem(g, 0.8)
+    f = P.init()
+    P.run(f, 0, 300)
+    sim = hlb.Simulation.create(g, 0.8, tables=[io.table for io in g.iolets])
+    hlb.hlb_set_state(sim.ctx, f, 300)
+    assert np.abs(sim.state() - f).max() <= 1e-15
+    P.run(f, 300, 200)
+    sim.step(200)
+    assert sim.t == 500
+    e = errors(*sim.macros(), *P.macros(f))
+    say("set_state f64:", fmt(e))
+    assert e["e_rho"] <= TOL_RHO and e["e_u"] <= TOL_U and e["e_wss"] <= TOL_WSS
+    sim.close()
+
+
+def test_save_load_and_snapshots_bitwise():
+    g = _small_tree()
+    tabs = _tree_tables(g)
+    a = _gpu_run(g, 0.6, 100, tables=tabs)
+    buf = hlb.hlb_state_save(a.ctx)
+    hlb.hlb_snapshot_alloc(a.ctx, 2)
+    hlb.hlb_snapshot_save(a.ctx, 1)
+    a.step(100)
+    ref = a.macros()
+    m_ref = hlb.hlb_mass_balance(a.ctx)
+    # restore from the device snapshot
+    hlb.hlb_snapshot_restore(a.ctx, 1)
+    assert a.t == 100
+    a.step(100)
+    for x, y in zip(ref, a.macros()):
+        assert np.array_equal(x, y)
+    # restore into a fresh context from the host copy
+    b = hlb.Simulation.create(g, 0.6, tables=tabs)
+    hlb.hlb_state_load(b.ctx, buf)
+    assert b.t == 100
+    b.step(100)
+    for x, y in zip(ref, b.macros()):
+        assert np.array_equal(x, y)
+    m_b = hlb.hlb_mass_balance(b.ctx)
+    assert abs(m_b[0] - m_ref[0]) <= 1e-12 * m_ref[0]
+    a.close()
+    b.close()
+
+
+def test_macros_device_torch():
+    import torch
+    g = G.cylinder()
+    sim = _gpu_run(g, 0.8, 100)
+    rho = torch.empty(g.n, dtype=torch.float64, device="cuda")
+    u = torch.empty((g.n, 3), dtype=torch.float64, device="cuda")
+    w = torch.empty(g.n, dtype=torch.float64, device="cuda")
+    hlb.hlb_set_stream(sim.ctx, torch.cuda.current_stream().cuda_stream)
+    hlb.hlb_macros_device(sim.ctx, rho, u, w)
+    torch.cuda.current_stream().synchronize()
+    hlb.hlb_set_stream(sim.ctx, None)
+    r2, u2, w2 = sim.macros()
+    assert np.array_equal(rho.cpu().numpy(), r2)
+    assert np.array_equal(u.cpu().numpy(), u2)
+    assert np.array_equal(w.cpu().numpy(), w2)
+    sim.close()
+
+
+def test_enomem_budget():
+    g = G.cylinder()
+    with pytest.raises(hlb.HLBError) as e:
+        hlb.Simulation.create(g, 0.8, max_device_bytes=1 << 16)
+    assert e.value.status == hlb.HLB_ENOMEM
+
+
+def test_enumeric_on_blow_up():
+    """tau close to 1/2 with a Mach-1 inlet blows up; the library reports it."""
+    g = G.cylinder(u_max=0.6)
+    sim = hlb.Simulation.create(g, 0.5000001, tables=[io.table for io in g.iolets])
+    sim.step(3000)
+    with pytest.raises(hlb.HLBError) as e:
+        hlb.hlb_mass_balance(sim.ctx)
+    assert e.value.status == hlb.HLB_ENUMERIC
+    sim.close()
+
+
+def test_time_and_zero_steps():
+    g = G.cylinder()
+    sim = _gpu_run(g, 0.8, 0)
+    assert sim.t == 0
+    rho, u, wss = sim.macros()
+    assert np.abs(rho - 1.0).max() <= 1e-15 and np.all(u == 0.0) and wss.max() <= 1e-20
+    sim.step(0)
+    assert sim.t == 0
+    sim.close()
