@@ -10,13 +10,13 @@ the shifted FP32 and FP16 storages.
 
 Prints ONE JSON line:
   value       MLUPS of the FP64 run (eq. (9): sites x steps / (s x 1e6))
-  roofline    the bulk+wall kernel (the dominant one) against 8 TB/s:
+  roofline    the step kernel (the only kernel of a step) against 8 TB/s:
               algorithmic bytes per launch (38 population loads/stores +
-              18 int32 pull entries per site, times the sites of that launch)
-              over its mean launch duration from HIP events on its stream
+              18 int32 pull entries per site, times all sites) over its
+              mean launch duration from HIP events on its stream
   cpu_baseline  the FP64 oracle on the host cores, on a bounded sample of
               the same workload (a few steps of the full geometry)
-  storages    MLUPS, bulk-kernel GB/s and fraction of peak for f64/f32/f16
+  storages    MLUPS, step-kernel GB/s and fraction of peak for f64/f32/f16
 """
 from __future__ import annotations
 
@@ -52,15 +52,15 @@ def kernel_source_hash():
     return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
 
 
-def stored_traffic(storage, n_bulk):
-    """HBM bytes per bulk launch from the committed rocprofv3 counter summary,
-    if it was taken on the current kernel source; else None."""
+def stored_traffic(storage, n_sites):
+    """HBM bytes per step-kernel launch from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel source and workload; else None."""
     p = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(p):
         return None
     d = json.load(open(p))
     e = d.get(storage)
-    if not e or e.get("kernel_sha") != kernel_source_hash() or e.get("n_bulk") != n_bulk:
+    if not e or e.get("kernel_sha") != kernel_source_hash() or e.get("n_sites") != n_sites:
         return None
     return e.get("bytes_per_launch")
 
@@ -86,35 +86,20 @@ def run_storage(g, tables, tau, storage, steps, warmup):
     m, r = hlb.hlb_mass_balance(sim.ctx)
     sim.close()
     n = info["n_sites"]
-    n_bulk = info["group_sites"][0]
     bpl = info["bytes_per_lup"]
     mlups = n * steps / dt / 1e6
-    achieved = bpl * n_bulk / (st["bulk_kernel_ms"] * 1e-3) / 1e9
-    return dict(storage=storage, n_sites=n, n_bulk=n_bulk, bytes_per_lup=bpl, ms_per_step=dt / steps * 1e3,
-                mlups=mlups, alg_gbs=bpl * n * steps / dt / 1e9, bulk_kernel_ms=st["bulk_kernel_ms"],
-                iolet_kernel_ms=st["iolet_kernel_ms"], event_step_ms=st["step_ms"], bulk_gbs=achieved,
+    # one step kernel updates every site of every group
+    achieved = bpl * n / (st["kernel_ms"] * 1e-3) / 1e9
+    return dict(storage=storage, n_sites=n, bytes_per_lup=bpl, ms_per_step=dt / steps * 1e3,
+                mlups=mlups, alg_gbs=bpl * n * steps / dt / 1e9, kernel_ms=st["kernel_ms"],
+                event_step_ms=st["step_ms"], kernel_gbs=achieved,
                 frac=achieved / PEAK_GBS, mass=m, mass_residual_rel=r / m)
 
 
 def copy_ceiling(nbytes=4 << 30, reps=20):
-    """A plain device-to-device copy: the practical HBM ceiling."""
-    import torch
-    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
-    b = torch.empty_like(a)
-    a.fill_(1.0)
-    for _ in range(3):
-        b.copy_(a)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(reps):
-        b.copy_(a)
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / reps
-    del a, b
-    torch.cuda.empty_cache()
-    return 2 * nbytes / (ms * 1e-3) / 1e9
+    """A plain HIP device-to-device copy (in libhlb): the practical HBM ceiling."""
+    from paper_2202_11770_amd import hlb
+    return hlb.hlb_copy_bandwidth(nbytes, reps)
 
 
 def cpu_baseline(g, tables, tau, budget_s=15.0):
@@ -160,8 +145,8 @@ def main():
         t1 = time.time()
         results[st] = run_storage(g, tables, tau, st, args.steps, args.warmup)
         r = results[st]
-        log(f"{st}: {r['mlups']:.0f} MLUPS, {r['ms_per_step']:.3f} ms/step, bulk kernel {r['bulk_kernel_ms']:.3f} ms "
-            f"= {r['bulk_gbs']:.0f} GB/s ({100 * r['frac']:.1f}% of 8 TB/s), mass residual {r['mass_residual_rel']:.2e} "
+        log(f"{st}: {r['mlups']:.0f} MLUPS, {r['ms_per_step']:.3f} ms/step, step kernel {r['kernel_ms']:.3f} ms "
+            f"= {r['kernel_gbs']:.0f} GB/s ({100 * r['frac']:.1f}% of 8 TB/s), mass residual {r['mass_residual_rel']:.2e} "
             f"({time.time() - t1:.1f}s)")
     main_st = args.storages.split(",")[0]
     R = results[main_st]
@@ -172,7 +157,7 @@ def main():
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(g, tables, tau)
         log(f"cpu baseline: {cpu}")
-    traffic = stored_traffic(main_st, R["n_bulk"])
+    traffic = stored_traffic(main_st, R["n_sites"])
     out = {
         "metric": "MLUPS & achieved HBM GB/s, FP64 vs FP32/FP16 storage at stated error",
         "value": round(R["mlups"], 2),
@@ -188,16 +173,17 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"bifurcating tree, {g.n} fluid sites (seed 2, 8 generations), tau 0.6, "
                                f"1 Ladd inlet + 256 pressure outlets, storage {main_st}",
-                   "n_sites": g.n, "storage": main_st, "order": "brick", "parallelism": "single GPU"},
-        "roofline": {"bound": "hbm", "achieved": round(R["bulk_gbs"], 1), "peak": PEAK_GBS, "unit": "GB/s",
+                   "n_sites": g.n, "storage": main_st, "order": "lex", "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": round(R["kernel_gbs"], 1), "peak": PEAK_GBS, "unit": "GB/s",
                      "frac": round(R["frac"], 4), "traffic": traffic,
-                     "kernel": "k_step_bulk (bulk+wall group)",
-                     "bytes_per_site": R["bytes_per_lup"], "sites_per_launch": R["n_bulk"],
-                     "mean_launch_ms": round(R["bulk_kernel_ms"], 5)},
+                     "kernel": "k_step (all site groups, one launch per step)",
+                     "bytes_per_site": R["bytes_per_lup"], "sites_per_launch": R["n_sites"],
+                     "mean_launch_ms": round(R["kernel_ms"], 5)},
         "cpu_baseline": cpu,
         "copy_ceiling_gbs": copy_gbs,
         "storages": {k: {"mlups": round(v["mlups"], 1), "ms_per_step": round(v["ms_per_step"], 4),
-                         "bulk_gbs": round(v["bulk_gbs"], 1), "frac": round(v["frac"], 4),
+                         "kernel_ms": round(v["kernel_ms"], 5),
+                         "kernel_gbs": round(v["kernel_gbs"], 1), "frac": round(v["frac"], 4),
                          "bytes_per_lup": v["bytes_per_lup"],
                          "gain_vs_f64": round(v["mlups"] / results[main_st]["mlups"], 3),
                          "mass_residual_rel": v["mass_residual_rel"]} for k, v in results.items()},

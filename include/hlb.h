@@ -84,9 +84,9 @@ enum {
 /* Internal site order (all keep the six types grouped). */
 typedef enum {
   HLB_ORDER_INPUT = 0,  /* caller order within each group */
-  HLB_ORDER_LEX = 1,    /* lexicographic (z, y, x) */
+  HLB_ORDER_LEX = 1,    /* lexicographic (z, y, x) (default) */
   HLB_ORDER_MORTON = 2, /* Morton (Z-order) curve */
-  HLB_ORDER_BRICK = 3   /* Morton order of 4x4x4 bricks, lexicographic inside (default) */
+  HLB_ORDER_BRICK = 3   /* Morton order of 4x4x4 bricks, lexicographic inside */
 } hlb_order;
 
 enum { HLB_IOLET_VELOCITY = 0, HLB_IOLET_PRESSURE = 1 };
@@ -113,9 +113,10 @@ typedef struct {
 
 typedef struct {
   int32_t storage;     /* hlb_storage (default HLB_F64) */
-  int32_t order;       /* hlb_order (default HLB_ORDER_BRICK) */
-  int32_t xcd_remap;   /* 1 (default): give each of the 8 XCDs a contiguous
-                          range of the site list; 0: plain block order */
+  int32_t order;       /* hlb_order (default HLB_ORDER_LEX) */
+  int32_t xcd_remap;   /* K > 0: renumber the bulk kernel's workgroups so that
+                          each of the 8 XCDs gets K consecutive tiles of every
+                          window of 8K tiles (default 2); 0: plain block order */
   int32_t reserved;    /* must be 0 */
   double rho0;         /* reference density (default 1.0) */
   int64_t max_device_bytes; /* 0: no limit; otherwise HLB_ENOMEM above it */
@@ -125,7 +126,7 @@ typedef struct {
 hlb_status hlb_default_options(hlb_options *opt);
 
 /* Create a simulation (Sec. 3.2.1: device set-up).
- *   n_sites   number of fluid sites, 1 <= n_sites < 2^31 - 2^12
+ *   n_sites   number of fluid sites, 1 <= n_sites < 2^30 - 2^12
  *   coords    [n][3] int32 lattice coordinates, each in [0, 2^20)
  *   site_type [n] uint8, HLB_SITE_*; must agree with the link codes
  *   nbr       [n][19] int32 push-direction table: nbr[x][i] = id of the site
@@ -205,20 +206,23 @@ typedef struct {
                                inlet+wall, outlet+wall, (unused) */
   int32_t storage;          /* hlb_storage */
   int32_t order;            /* hlb_order */
-  double bytes_per_lup;     /* algorithmic HBM bytes per lattice-site update */
+  double bytes_per_lup;     /* algorithmic HBM bytes per lattice-site update: 19
+                               population loads + 19 stores + table_bytes_per_site */
   int64_t device_bytes;     /* device memory held by the context */
+  double table_bytes_per_site; /* neighbour-table bytes read per site update */
+  int64_t n_segments;       /* segments of the bulk+wall group's table */
 } hlb_info_t;
 hlb_status hlb_info(const hlb_ctx *ctx, hlb_info_t *info);
 
-/* Kernel timing (HIP events around each launch of the bulk kernel) while
- * enabled; hlb_stats reports the steps timed and the mean bulk-kernel and
- * whole-step durations in milliseconds. */
+/* Kernel timing (HIP events on the context stream around each launch of the
+ * step kernel) while enabled; hlb_stats reports the steps timed, the mean
+ * duration of the step kernel and the mean stream time per step, in
+ * milliseconds.  Enabling or disabling resets the counts. */
 hlb_status hlb_set_timing(hlb_ctx *ctx, int32_t enable);
 typedef struct {
-  int64_t steps;            /* steps timed since timing was enabled */
-  double bulk_kernel_ms;    /* mean duration of the bulk+wall kernel */
-  double iolet_kernel_ms;   /* mean duration of the iolet kernel */
-  double step_ms;           /* mean wall time of a whole step on the stream */
+  int64_t steps;     /* steps timed since timing was enabled */
+  double kernel_ms;  /* mean duration of one step kernel (all site groups) */
+  double step_ms;    /* mean stream time per step, first to last timed event */
 } hlb_stats_t;
 hlb_status hlb_stats(hlb_ctx *ctx, hlb_stats_t *stats);
 
@@ -237,6 +241,13 @@ hlb_status hlb_state_load(hlb_ctx *ctx, const void *host_buf);
 
 /* Wait for all work queued on the context stream. */
 hlb_status hlb_sync(hlb_ctx *ctx);
+
+/* Measurement aid, not part of the method: bandwidth in GB/s (read + write
+ * bytes over time) of a plain non-temporal device-to-device copy of `bytes`
+ * (>= 1 MiB, multiple of 16) repeated `reps` times on the null stream of the
+ * current device -- the practical ceiling for the step kernel.  Allocates and
+ * frees two buffers of `bytes`. */
+hlb_status hlb_copy_bandwidth(int64_t bytes, int32_t reps, double *gbs);
 
 /* Message of the last failure on this thread ("" if none). */
 const char *hlb_last_error(void);

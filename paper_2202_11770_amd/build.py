@@ -34,13 +34,16 @@ def build(verbose: bool = False, extra_hipcc=()) -> str:
     os.makedirs(BUILD, exist_ok=True)
     inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
     kobj = os.path.join(BUILD, "hlb_kernels.o")
+    cobj = os.path.join(BUILD, "hlb_copy.o")
     robj = os.path.join(BUILD, "hlb_runtime.o")
     _run([os.path.join(ROCM, "bin", "hipcc"), *HIPCC_FLAGS, *extra_hipcc, *inc, "-c",
           os.path.join(CSRC, "hlb_kernels.hip"), "-o", kobj], verbose)
+    _run([os.path.join(ROCM, "bin", "hipcc"), *HIPCC_FLAGS, *inc, "-c",
+          os.path.join(CSRC, "hlb_copy.hip"), "-o", cobj], verbose)
     _run(["g++", "-O2", "-std=c++17", "-fPIC", "-fopenmp", "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(ROCM, "include"),
           *inc, "-c", os.path.join(CSRC, "hlb_runtime.cpp"), "-o", robj], verbose)
     tmp = LIB + ".tmp"
-    _run(["g++", "-shared", "-fopenmp", kobj, robj, "-o", tmp, "-L", os.path.join(ROCM, "lib"),
+    _run(["g++", "-shared", "-fopenmp", kobj, cobj, robj, "-o", tmp, "-L", os.path.join(ROCM, "lib"),
           "-Wl,-rpath," + os.path.join(ROCM, "lib"), "-lamdhip64"], verbose)
     os.replace(tmp, LIB)
     return LIB

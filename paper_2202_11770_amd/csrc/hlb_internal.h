@@ -16,6 +16,15 @@ constexpr int kGroups = 5;
 // Each group range starts on a multiple of this many sites, so that no
 // 64-lane wavefront straddles two groups (wavefront-uniform code paths).
 constexpr int64_t kGroupAlign = 256;
+// Bulk+wall group pull table: positions [0, n0) are cut into segments of
+// consecutive positions whose 18 incoming links have the same source offsets
+// (source position minus own position; a wall link's offset is
+// (opp(i) - i) np, which lands on the site's own slot of direction opp(i)).
+// Each segment stores its offsets once, as a row of kSegRow int32 (18 used,
+// padded for 16-byte loads); each position stores a one-byte segment index
+// relative to the first segment of its kSegBlock-position block.
+constexpr int kSegRow = 20;
+constexpr int64_t kSegBlock = 256;
 
 struct IoletDev {
   int32_t kind;     // HLB_IOLET_VELOCITY / HLB_IOLET_PRESSURE
@@ -32,12 +41,16 @@ struct Layout {
   int64_t gcnt[kGroups] = {0};
   int64_t io_begin = 0;         // first position of the iolet groups
   int64_t nio = 0;              // np - io_begin
+  int64_t nseg = 0;             // segments of the bulk+wall group
 };
 
 struct DevPtrs {
   void *f[2] = {nullptr, nullptr};  // population buffers, [19][np] of the storage type
-  int32_t *nbr = nullptr;           // pull table [18][np]: source position of population i
-                                    // (i = 1..18), or the link code (< 0)
+  int32_t *seg_off = nullptr;       // [nseg][kSegRow] bulk+wall source offsets per segment
+  int32_t *seg_base = nullptr;      // [ceil(n0 / kSegBlock)] first segment of each block
+  uint8_t *seg_delta = nullptr;     // [n0] segment of each position minus its block's first
+  int32_t *nbr_io = nullptr;        // iolet groups' pull table [18][nio]: source position of
+                                    // population i (i = 1..18), or the link code (< 0)
   int32_t *order = nullptr;         // [np] caller id of each position (-1 for padding)
   double *corr = nullptr;           // [18][nio] Ladd coefficients of iolet-group links
   IoletDev *io = nullptr;           // [n_iolets]
@@ -53,15 +66,15 @@ struct LaunchCfg {
   int storage = HLB_F64;
   double tau = 0.8;
   double rho0 = 1.0;
-  bool xcd_remap = true;
+  int xcd_chunk = 0;  // blocks per XCD chunk (0: plain block order)
   bool porous = false;
 };
 
 // ---- launchers (hlb_kernels.hip); all asynchronous on `s` ----
 // One update t -> t+1: reads buffer `src`, writes buffer 1-src.
+// ev_begin / ev_end (may be null) are recorded around the step kernel.
 hipError_t launch_step(const LaunchCfg &cfg, const Layout &L, const DevPtrs &d, int src, int64_t t,
-                       hipStream_t s, hipEvent_t ev_bulk_begin, hipEvent_t ev_bulk_end,
-                       hipEvent_t ev_io_end);
+                       hipStream_t s, hipEvent_t ev_begin, hipEvent_t ev_end);
 // Both buffers := equilibrium of (rho, u) given per caller id in staging
 // (staging: [n][4] doubles rho, ux, uy, uz) or rest if staging is null.
 hipError_t launch_init_eq(const LaunchCfg &cfg, const Layout &L, const DevPtrs &d,

@@ -12,9 +12,10 @@
 // the site's own, coalesced, slots.
 //
 // Sites are grouped by collision-streaming type (Sec. 3.2.2): positions
-// [0, n0) hold the merged bulk+wall group, handled by k_step_bulk with a
-// branch-free address select for bounce-back; the four iolet groups follow,
-// each starting on a 256-site boundary, and are handled by k_step_iolet.
+// [0, n0) hold the merged bulk+wall group, whose pull table encodes
+// bounce-back as a plain indexed load; the four iolet groups follow, each
+// starting on a 256-site boundary, with the boundary rules applied per link.
+// k_step runs both code paths in one launch, one group per workgroup.
 //
 // The method is bound by HBM bandwidth (~0.7 flop per byte in FP64), so
 // nothing here uses the matrix cores.
@@ -70,17 +71,27 @@ __device__ inline C rest(int i, C rho0) {
 __device__ inline double ld(const double *p) { return *p; }
 __device__ inline float ld(const float *p) { return *p; }
 __device__ inline float ld(const _Float16 *p) { return static_cast<float>(*p); }
-__device__ inline void st(double *p, double v) { *p = v; }
-__device__ inline void st(float *p, float v) { *p = v; }
-__device__ inline void st(_Float16 *p, float v) { *p = static_cast<_Float16>(v); }  // round to nearest even
+// Population stores and pull-table loads stream through HBM once per step:
+// non-temporal, so that they do not displace the gathered lines from cache.
+__device__ inline void st(double *p, double v) { __builtin_nontemporal_store(v, p); }
+__device__ inline void st(float *p, float v) { __builtin_nontemporal_store(v, p); }
+__device__ inline void st(_Float16 *p, float v) {
+  __builtin_nontemporal_store(static_cast<_Float16>(v), p);  // round to nearest even
+}
+__device__ inline uint8_t ld_stream(const uint8_t *p) { return __builtin_nontemporal_load(p); }
 
-// Give each XCD (workgroups are dealt to the 8 XCDs round-robin) one
-// contiguous range of blocks, so that neighbouring sites share an L2.
-__device__ inline int64_t block_id(bool remap) {
-  const int64_t b = blockIdx.x;
-  if (!remap) return b;
-  const int64_t G = gridDim.x, q = G >> 3, r = G & 7, x = b & 7, m = b >> 3;
-  return x * q + (x < r ? x : r) + m;
+// Workgroups are dealt to the 8 XCDs round-robin by block id.  With a chunk
+// size K > 0 the blocks are renumbered so that each XCD gets K consecutive
+// tiles of every window of 8K tiles: neighbouring tiles then share that
+// XCD's L2 while the chip as a whole still sweeps the site list in order.
+// The last, partial window keeps the plain order.
+__device__ inline int64_t block_id(int64_t b, int64_t G, int chunk) {
+  if (chunk <= 0) return b;
+  const int64_t win = 8 * (int64_t)chunk;
+  const int64_t w = b / win;
+  if ((w + 1) * win > G) return b;
+  const int64_t r = b - w * win;
+  return w * win + (r & 7) * chunk + (r >> 3);
 }
 
 __device__ inline double wave_sum(double v) {
@@ -130,7 +141,10 @@ __device__ inline void collide(C (&s)[Q], C omega, C rho0) {
 }
 
 struct GatherArgs {
-  const int32_t *nbr;
+  const int32_t *seg_off;     // bulk+wall group: per-segment source offsets
+  const int32_t *seg_base;
+  const uint8_t *seg_delta;
+  const int32_t *nbr_io;      // iolet groups: [18][nio] sources / link codes
   int64_t np;
   int64_t io_begin;
   int64_t nio;
@@ -141,6 +155,30 @@ struct GatherArgs {
   const double *phi;   // porosity or null
   double rho0;
 };
+
+static_assert(kBlock == kSegBlock, "one segment base per workgroup");
+static_assert(kSegRow == 20, "segment rows are five 16-byte vectors");
+
+// Source offsets of the 18 incoming links of bulk+wall position p, whose
+// kSegBlock-position block is blk: off[i-1] = source - p, the source being
+// a fluid position in [0, np) or, for a wall link, the site's own slot of
+// direction opp(i) (offset +-np, outside [0, np)).
+__device__ inline void bulk_offsets(const GatherArgs &a, int64_t p, int64_t blk, int32_t (&off)[Q - 1]) {
+  const int32_t s = a.seg_base[blk] + (int32_t)ld_stream(a.seg_delta + p);
+  const int4 *row = reinterpret_cast<const int4 *>(a.seg_off + (int64_t)s * kSegRow);
+  int4 r[5];
+#pragma unroll
+  for (int k = 0; k < 5; ++k) r[k] = row[k];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    off[4 * k] = r[k].x;
+    off[4 * k + 1] = r[k].y;
+    off[4 * k + 2] = r[k].z;
+    off[4 * k + 3] = r[k].w;
+  }
+  off[16] = r[4].x;
+  off[17] = r[4].y;
+}
 
 // Pre-collision populations of site p at time t+1, gathered from the
 // post-collision buffer A of time t (stored values s = f - off), with the
@@ -153,20 +191,24 @@ struct GatherArgs {
 //                                 u the site's velocity at time t
 // Returns the mass the boundary rules added (filled - reflected).
 // IOLET = false: the site has only fluid and wall links.
+// blk: the kSegBlock-position block of p (bulk+wall group only).
 template <bool IOLET, bool POROUS, bool SH, typename T, typename C>
-__device__ inline C gather(const T *__restrict__ A, int64_t p, const GatherArgs &a, C (&g)[Q]) {
+__device__ inline C gather(const T *__restrict__ A, int64_t p, int64_t blk, const GatherArgs &a, C (&g)[Q]) {
   const int64_t np = a.np;
   C flux = 0;
   if constexpr (!IOLET) {
+    // Bulk+wall group: every link, bounce-back included, is a plain load at
+    // p + off from direction array i; the offsets are fetched before the
+    // 18 gathers are issued.
+    int32_t off[Q - 1];
+    bulk_offsets(a, p, blk, off);
     g[0] = ld(A + p);
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
-      const int32_t j = a.nbr[(int64_t)(i - 1) * np + p];
-      // branch-free: fluid source j, or the site's own reflected slot
-      const T *src = (j >= 0) ? (A + (int64_t)i * np + j) : (A + (int64_t)opp(i) * np + p);
-      C v = ld(src);
+      const int64_t j = p + (int64_t)off[i - 1];
+      C v = ld(A + (int64_t)i * np + j);
       if constexpr (POROUS) {
-        if (j < 0) {
+        if ((uint64_t)j >= (uint64_t)np) {
           const C nv = v - C(a.phi[p]) * (v - rest<SH, C>(i, C(a.rho0)));
           flux += nv - v;
           v = nv;
@@ -186,7 +228,7 @@ __device__ inline C gather(const T *__restrict__ A, int64_t p, const GatherArgs 
     g[0] = own[0];
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
-      const int32_t code = a.nbr[(int64_t)(i - 1) * np + p];
+      const int32_t code = a.nbr_io[(int64_t)(i - 1) * a.nio + (p - a.io_begin)];
       if (code >= 0) {
         g[i] = ld(A + (int64_t)i * np + code);
         continue;
@@ -217,42 +259,46 @@ __device__ inline C gather(const T *__restrict__ A, int64_t p, const GatherArgs 
 
 // ---------------------------------------------------------------- step ----
 
+// One launch per step covers every group (Sec. 3.2.2's per-type kernels as
+// block-uniform code paths of a single launch): the first nb_io blocks take
+// the iolet groups, so that their longer-latency work starts first and
+// overlaps the bulk blocks; the remaining blocks take the bulk+wall group.
+// Every block, hence every wavefront, runs one group's code path only.
 template <typename T, bool POROUS>
-__global__ __launch_bounds__(kBlock) void k_step_bulk(const T *__restrict__ A, T *__restrict__ B,
-                                                      GatherArgs a, int64_t n0, int remap,
-                                                      typename Acc<T>::type omega, double *acc) {
+__global__ __launch_bounds__(kBlock) void k_step(const T *__restrict__ A, T *__restrict__ B, GatherArgs a,
+                                                 const int32_t *__restrict__ order, int64_t n0, int64_t nb_io,
+                                                 int64_t nb_bulk, int xcd_chunk, typename Acc<T>::type omega,
+                                                 double *acc) {
   using C = typename Acc<T>::type;
-  const int64_t p = block_id(remap) * kBlock + threadIdx.x;
+  constexpr bool SH = kShifted<T>;
+  const int64_t b = blockIdx.x;
   C flux = 0;
-  if (p < n0) {
-    C g[Q];
-    flux = gather<false, POROUS, kShifted<T>>(A, p, a, g);
-    collide<kShifted<T>>(g, omega, C(a.rho0));
+  if (b < nb_io) {
+    const int64_t p = a.io_begin + b * kBlock + threadIdx.x;
+    if (p < a.np && order[p] >= 0) {
+      C g[Q];
+      flux = gather<true, POROUS, SH>(A, p, 0, a, g);
+      collide<SH>(g, omega, C(a.rho0));
 #pragma unroll
-    for (int i = 0; i < Q; ++i) st(B + (int64_t)i * a.np + p, g[i]);
-  }
-  if constexpr (POROUS) {
+      for (int i = 0; i < Q; ++i) st(B + (int64_t)i * a.np + p, g[i]);
+    }
     const double s = wave_sum(double(flux));
     if ((threadIdx.x & 63) == 0 && s != 0.0) atomicAdd(acc, s);
-  }
-}
-
-template <typename T, bool POROUS>
-__global__ __launch_bounds__(kBlock) void k_step_iolet(const T *__restrict__ A, T *__restrict__ B,
-                                                       GatherArgs a, const int32_t *__restrict__ order,
-                                                       typename Acc<T>::type omega, double *acc) {
-  using C = typename Acc<T>::type;
-  const int64_t p = a.io_begin + (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  C flux = 0;
-  if (p < a.np && order[p] >= 0) {
-    C g[Q];
-    flux = gather<true, POROUS, kShifted<T>>(A, p, a, g);
-    collide<kShifted<T>>(g, omega, C(a.rho0));
+  } else {
+    const int64_t blk = block_id(b - nb_io, nb_bulk, xcd_chunk);
+    const int64_t p = blk * kBlock + threadIdx.x;
+    if (p < n0) {
+      C g[Q];
+      flux = gather<false, POROUS, SH>(A, p, blk, a, g);
+      collide<SH>(g, omega, C(a.rho0));
 #pragma unroll
-    for (int i = 0; i < Q; ++i) st(B + (int64_t)i * a.np + p, g[i]);
+      for (int i = 0; i < Q; ++i) st(B + (int64_t)i * a.np + p, g[i]);
+    }
+    if constexpr (POROUS) {
+      const double s = wave_sum(double(flux));
+      if ((threadIdx.x & 63) == 0 && s != 0.0) atomicAdd(acc, s);
+    }
   }
-  const double s = wave_sum(double(flux));
-  if ((threadIdx.x & 63) == 0 && s != 0.0) atomicAdd(acc, s);
 }
 
 // ------------------------------------------------------- init / state ----
@@ -327,9 +373,9 @@ __global__ __launch_bounds__(kBlock) void k_macros(const T *__restrict__ A, Gath
 #pragma unroll
     for (int i = 0; i < Q; ++i) g[i] = ld(A + (int64_t)i * a.np + p);
   } else if (p < a.io_begin) {
-    gather<false, POROUS, SH>(A, p, a, g);
+    gather<false, POROUS, SH>(A, p, p / kBlock, a, g);
   } else {
-    gather<true, POROUS, SH>(A, p, a, g);
+    gather<true, POROUS, SH>(A, p, 0, a, g);
   }
   if (f_o) {
 #pragma unroll
@@ -347,12 +393,18 @@ __global__ __launch_bounds__(kBlock) void k_macros(const T *__restrict__ A, Gath
   }
   if (!wss_o) return;
   // wall normal: normalised sum of the directions whose links hit a wall;
-  // pull entry i describes the link leaving along opp(i) = -c_i
+  // pull entry i describes the link leaving along opp(i) = -c_i (a wall
+  // link is coded -1 in the iolet groups, outside [0, np) in the bulk group)
   double nx = 0, ny = 0, nz = 0;
   bool any = false;
+  const bool bulk = p < a.io_begin;
+  int32_t off[Q - 1];
+  if (bulk) bulk_offsets(a, p, p / kBlock, off);
 #pragma unroll
   for (int i = 1; i < Q; ++i) {
-    if (a.nbr[(int64_t)(i - 1) * a.np + p] == HLB_LINK_WALL) {
+    const bool wall = bulk ? (uint64_t)(p + (int64_t)off[i - 1]) >= (uint64_t)a.np
+                           : a.nbr_io[(int64_t)(i - 1) * a.nio + (p - a.io_begin)] == HLB_LINK_WALL;
+    if (wall) {
       any = true;
       nx -= cx(i);
       ny -= cy(i);
@@ -435,7 +487,10 @@ __global__ void k_zero(double *p, int64_t n) {
 
 GatherArgs make_args(const LaunchCfg &cfg, const Layout &L, const DevPtrs &d, int64_t t) {
   GatherArgs a;
-  a.nbr = d.nbr;
+  a.seg_off = d.seg_off;
+  a.seg_base = d.seg_base;
+  a.seg_delta = d.seg_delta;
+  a.nbr_io = d.nbr_io;
   a.np = L.np;
   a.io_begin = L.io_begin;
   a.nio = L.nio;
@@ -452,30 +507,26 @@ inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBl
 
 template <typename T>
 hipError_t step_impl(const LaunchCfg &cfg, const Layout &L, const DevPtrs &d, int src, int64_t t,
-                     hipStream_t s, hipEvent_t e0, hipEvent_t e1, hipEvent_t e2) {
+                     hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   using C = typename Acc<T>::type;
   const T *A = static_cast<const T *>(d.f[src]);
   T *B = static_cast<T *>(d.f[1 - src]);
   const GatherArgs a = make_args(cfg, L, d, t);
   const C omega = C(1.0 / cfg.tau);
   const int64_t n0 = L.gcnt[0];
+  const int64_t nb_io = (L.nio + kBlock - 1) / kBlock, nb_bulk = (n0 + kBlock - 1) / kBlock;
+  const unsigned grid = (unsigned)(nb_io + nb_bulk);
   hipError_t er;
   if (e0 && (er = hipEventRecord(e0, s)) != hipSuccess) return er;
-  if (n0 > 0) {
+  if (grid > 0) {
     if (cfg.porous)
-      k_step_bulk<T, true><<<blocks_for(n0), kBlock, 0, s>>>(A, B, a, n0, cfg.xcd_remap, omega, d.acc);
+      k_step<T, true><<<grid, kBlock, 0, s>>>(A, B, a, d.order, n0, nb_io, nb_bulk, cfg.xcd_chunk, omega, d.acc);
     else
-      k_step_bulk<T, false><<<blocks_for(n0), kBlock, 0, s>>>(A, B, a, n0, cfg.xcd_remap, omega, d.acc);
+      k_step<T, false><<<grid, kBlock, 0, s>>>(A, B, a, d.order, n0, nb_io, nb_bulk, cfg.xcd_chunk, omega, d.acc);
   }
+  if ((er = hipGetLastError()) != hipSuccess) return er;
   if (e1 && (er = hipEventRecord(e1, s)) != hipSuccess) return er;
-  if (L.nio > 0) {
-    if (cfg.porous)
-      k_step_iolet<T, true><<<blocks_for(L.nio), kBlock, 0, s>>>(A, B, a, d.order, omega, d.acc);
-    else
-      k_step_iolet<T, false><<<blocks_for(L.nio), kBlock, 0, s>>>(A, B, a, d.order, omega, d.acc);
-  }
-  if (e2 && (er = hipEventRecord(e2, s)) != hipSuccess) return er;
-  return hipGetLastError();
+  return hipSuccess;
 }
 
 template <typename T>
@@ -530,8 +581,8 @@ hipError_t mass_impl(const Layout &L, const DevPtrs &d, int src, hipStream_t s) 
   }
 
 hipError_t launch_step(const LaunchCfg &cfg, const Layout &L, const DevPtrs &d, int src, int64_t t,
-                       hipStream_t s, hipEvent_t e0, hipEvent_t e1, hipEvent_t e2) {
-  HLB_DISPATCH(cfg.storage, step_impl<T>(cfg, L, d, src, t, s, e0, e1, e2));
+                       hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  HLB_DISPATCH(cfg.storage, step_impl<T>(cfg, L, d, src, t, s, e0, e1));
 }
 
 hipError_t launch_init_eq(const LaunchCfg &cfg, const Layout &L, const DevPtrs &d, const double *staging,

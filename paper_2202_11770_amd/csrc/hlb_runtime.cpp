@@ -113,7 +113,7 @@ void psort(std::vector<KeyId> &v) {
 }
 
 struct TimedStep {
-  hipEvent_t e[3];
+  hipEvent_t e[2];
 };
 
 }  // namespace
@@ -130,10 +130,11 @@ struct hlb_ctx {
   int64_t t = 0;
   int64_t t0 = 0;       // last (re)initialisation
   double m0 = 0.0;      // mass at t0
-  int order = HLB_ORDER_BRICK;
+  int order = HLB_ORDER_LEX;
   int64_t max_bytes = 0;
   int64_t dev_bytes = 0;
   int64_t staging_len = 0;             // doubles in d.io_scratch
+  int64_t table_bytes = 0;             // device bytes of the pull tables
   std::vector<int32_t> order_host;     // [np] caller id per position
   std::vector<hlb_iolet> iolets;
   std::vector<std::vector<double>> tables;
@@ -142,7 +143,7 @@ struct hlb_ctx {
   std::vector<TimedStep> pool;
   size_t n_timed = 0;
   int64_t steps_timed = 0;
-  double sum_bulk = 0, sum_io = 0, sum_step = 0;
+  double sum_kernel = 0, sum_step = 0;
   // snapshots
   struct Snap {
     void *f[2] = {nullptr, nullptr};
@@ -176,7 +177,7 @@ hlb_status dev_alloc(hlb_ctx *c, void **p, size_t bytes) {
 
 void free_all(hlb_ctx *c) {
   auto F = [](void *p) { if (p) (void)hipFree(p); };
-  F(c->d.f[0]); F(c->d.f[1]); F(c->d.nbr); F(c->d.order); F(c->d.corr); F(c->d.io); F(c->d.tables);
+  F(c->d.f[0]); F(c->d.f[1]); F(c->d.nbr_io); F(c->d.seg_off); F(c->d.seg_base); F(c->d.seg_delta); F(c->d.order); F(c->d.corr); F(c->d.io); F(c->d.tables);
   F(c->d.phi); F(c->d.acc); F(c->d.partial); F(c->d.io_scratch);
   for (auto &s : c->snaps) { F(s.f[0]); F(s.f[1]); F(s.acc); }
   c->snaps.clear();
@@ -278,8 +279,8 @@ const char *hlb_last_error(void) { return g_err.c_str(); }
 hlb_status hlb_default_options(hlb_options *opt) {
   if (!opt) return fail(HLB_EINVAL, "null options");
   opt->storage = HLB_F64;
-  opt->order = HLB_ORDER_BRICK;
-  opt->xcd_remap = 1;
+  opt->order = HLB_ORDER_LEX;
+  opt->xcd_remap = 2;
   opt->reserved = 0;
   opt->rho0 = 1.0;
   opt->max_device_bytes = 0;
@@ -292,7 +293,7 @@ hlb_status hlb_create(int64_t n, const int32_t *coords, const uint8_t *type, con
   if (!out) return fail(HLB_EINVAL, "out is null");
   *out = nullptr;
   if (!coords || !type || !nbr) return fail(HLB_EINVAL, "coords, site_type and nbr must be non-null");
-  if (n < 1 || n >= (int64_t)2147483647 - 4096) return fail(HLB_EINVAL, "n_sites=%lld out of range", (long long)n);
+  if (n < 1 || n >= (int64_t)(1 << 30) - 4096) return fail(HLB_EINVAL, "n_sites=%lld out of range", (long long)n);
   if (!(tau > 0.5) || !std::isfinite(tau)) return fail(HLB_EINVAL, "tau=%g must be finite and > 1/2", tau);
   if (n_iolets < 0 || (n_iolets > 0 && !iolets)) return fail(HLB_EINVAL, "bad iolet list");
   hlb_options opt;
@@ -301,7 +302,8 @@ hlb_status hlb_create(int64_t n, const int32_t *coords, const uint8_t *type, con
   if (opt.storage < HLB_F64 || opt.storage > HLB_F16_SHIFTED) return fail(HLB_EINVAL, "bad storage %d", opt.storage);
   if (opt.order < HLB_ORDER_INPUT || opt.order > HLB_ORDER_BRICK) return fail(HLB_EINVAL, "bad order %d", opt.order);
   if (!(opt.rho0 > 0.0) || !std::isfinite(opt.rho0)) return fail(HLB_EINVAL, "rho0 must be finite and > 0");
-  if (opt.reserved != 0 || opt.max_device_bytes < 0) return fail(HLB_EINVAL, "bad options");
+  if (opt.reserved != 0 || opt.max_device_bytes < 0 || opt.xcd_remap < 0 || opt.xcd_remap > (1 << 20))
+    return fail(HLB_EINVAL, "bad options");
   for (int k = 0; k < n_iolets; ++k) {
     const hlb_iolet &I = iolets[k];
     if (I.kind != HLB_IOLET_VELOCITY && I.kind != HLB_IOLET_PRESSURE) return fail(HLB_EINVAL, "iolet %d: bad kind", k);
@@ -369,7 +371,7 @@ hlb_status hlb_create(int64_t n, const int32_t *coords, const uint8_t *type, con
   c->cfg.storage = opt.storage;
   c->cfg.tau = tau;
   c->cfg.rho0 = opt.rho0;
-  c->cfg.xcd_remap = opt.xcd_remap != 0;
+  c->cfg.xcd_chunk = opt.xcd_remap;
   c->cfg.porous = false;
   c->order = opt.order;
   c->max_bytes = opt.max_device_bytes;
@@ -421,17 +423,52 @@ hlb_status hlb_create(int64_t n, const int32_t *coords, const uint8_t *type, con
   grp.clear();
   grp.shrink_to_fit();
 
-  // ---- pull table: population i of position p comes from the site at x - c_i ----
-  std::vector<int32_t> pull((size_t)18 * np, HLB_LINK_WALL);
+  // ---- pull tables: population i of position p comes from the site at x - c_i ----
+  // Iolet groups: per-link table of source positions or link codes
+  // (-1 wall, -(2+k) iolet k).
+  std::vector<int32_t> pull_io((size_t)18 * L.nio, HLB_LINK_WALL);
 #pragma omp parallel for schedule(static)
-  for (int64_t p = 0; p < np; ++p) {
-    const int32_t x = c->order_host[p];
+  for (int64_t q = 0; q < L.nio; ++q) {
+    const int32_t x = c->order_host[L.io_begin + q];
     if (x < 0) continue;
     for (int i = 1; i < Q; ++i) {
       const int32_t y = nbr[Q * (int64_t)x + OPP(i)];
-      pull[(size_t)(i - 1) * np + p] = y >= 0 ? inv[y] : y;
+      pull_io[(size_t)(i - 1) * L.nio + q] = y >= 0 ? inv[y] : y;
     }
   }
+  // Bulk+wall group: segmented source offsets (see kSegRow in hlb_internal.h).
+  const int64_t n0 = L.gcnt[0];
+  const int64_t nb0 = (n0 + kSegBlock - 1) / kSegBlock;
+  auto offset_of = [&](int64_t p, int i) -> int32_t {
+    const int32_t y = nbr[Q * (int64_t)c->order_host[p] + OPP(i)];
+    return y >= 0 ? (int32_t)(inv[y] - p) : (int32_t)((int64_t)(OPP(i) - i) * np);
+  };
+  std::vector<int32_t> segid(n0);
+#pragma omp parallel for schedule(static)
+  for (int64_t p = 0; p < n0; ++p) {
+    bool start = p == 0;
+    for (int i = 1; i < Q && !start; ++i) start = offset_of(p, i) != offset_of(p - 1, i);
+    segid[p] = start ? 1 : 0;
+  }
+  int64_t nseg = 0;
+  for (int64_t p = 0; p < n0; ++p) {
+    nseg += segid[p];
+    segid[p] = (int32_t)(nseg - 1);
+  }
+  L.nseg = nseg;
+  std::vector<int32_t> seg_off((size_t)kSegRow * std::max<int64_t>(nseg, 1), 0);
+  std::vector<int32_t> seg_base(std::max<int64_t>(nb0, 1), 0);
+  std::vector<uint8_t> seg_delta((size_t)std::max<int64_t>(nb0 * kSegBlock, 1), 0);
+#pragma omp parallel for schedule(static)
+  for (int64_t p = 0; p < n0; ++p) {
+    if (p == 0 || segid[p] != segid[p - 1])
+      for (int i = 1; i < Q; ++i) seg_off[(size_t)segid[p] * kSegRow + (i - 1)] = offset_of(p, i);
+    if (p % kSegBlock == 0) seg_base[p / kSegBlock] = segid[p];
+  }
+#pragma omp parallel for schedule(static)
+  for (int64_t p = 0; p < n0; ++p) seg_delta[p] = (uint8_t)(segid[p] - segid[(p / kSegBlock) * kSegBlock]);
+  segid.clear();
+  segid.shrink_to_fit();
   // ---- Ladd coefficients 6 w_i rho0 (c_i . v_k) W_k(x - c_i/2) of velocity-iolet links ----
   std::vector<double> corr((size_t)18 * L.nio, 0.0);
 #pragma omp parallel for schedule(static)
@@ -474,8 +511,9 @@ hlb_status hlb_create(int64_t n, const int32_t *coords, const uint8_t *type, con
   }
   const size_t fb = (size_t)Q * np * storage_bytes(opt.storage);
   const int64_t partial_len = 1 + 8192;
-  const size_t need = 2 * fb + 18 * np * sizeof(int32_t) + np * sizeof(int32_t) + corr.size() * sizeof(double) +
-                      partial_len * sizeof(double);
+  const size_t need = 2 * fb + pull_io.size() * sizeof(int32_t) + seg_off.size() * sizeof(int32_t) +
+                      seg_base.size() * sizeof(int32_t) + seg_delta.size() + np * sizeof(int32_t) +
+                      corr.size() * sizeof(double) + partial_len * sizeof(double);
   if (c->max_bytes > 0 && (int64_t)need > c->max_bytes) {
     delete c;
     return fail(HLB_ENOMEM, "needs %zu device bytes, budget is %lld", need, (long long)opt.max_device_bytes);
@@ -495,8 +533,16 @@ hlb_status hlb_create(int64_t n, const int32_t *coords, const uint8_t *type, con
   hlb_status st;
   if ((st = dev_alloc(c, &c->d.f[0], fb))) return bail(st);
   if ((st = dev_alloc(c, &c->d.f[1], fb))) return bail(st);
-  if ((st = dev_alloc(c, &p, 18 * np * sizeof(int32_t)))) return bail(st);
-  c->d.nbr = static_cast<int32_t *>(p);
+  if ((st = dev_alloc(c, &p, std::max<size_t>(1, pull_io.size()) * sizeof(int32_t)))) return bail(st);
+  c->d.nbr_io = static_cast<int32_t *>(p);
+  if ((st = dev_alloc(c, &p, seg_off.size() * sizeof(int32_t)))) return bail(st);
+  c->d.seg_off = static_cast<int32_t *>(p);
+  if ((st = dev_alloc(c, &p, seg_base.size() * sizeof(int32_t)))) return bail(st);
+  c->d.seg_base = static_cast<int32_t *>(p);
+  if ((st = dev_alloc(c, &p, seg_delta.size()))) return bail(st);
+  c->d.seg_delta = static_cast<uint8_t *>(p);
+  c->table_bytes = (int64_t)(pull_io.size() * sizeof(int32_t) + seg_off.size() * sizeof(int32_t) +
+                             seg_base.size() * sizeof(int32_t) + seg_delta.size());
   if ((st = dev_alloc(c, &p, np * sizeof(int32_t)))) return bail(st);
   c->d.order = static_cast<int32_t *>(p);
   if ((st = dev_alloc(c, &p, std::max<size_t>(1, corr.size()) * sizeof(double)))) return bail(st);
@@ -511,12 +557,13 @@ hlb_status hlb_create(int64_t n, const int32_t *coords, const uint8_t *type, con
     if (e != hipSuccess) return fail(HLB_EDEVICE, "hipMemcpy: %s", hipGetErrorString(e));
     return HLB_OK;
   };
-  if ((st = cp(c->d.nbr, pull.data(), pull.size() * sizeof(int32_t)))) return bail(st);
+  if (!pull_io.empty() && (st = cp(c->d.nbr_io, pull_io.data(), pull_io.size() * sizeof(int32_t)))) return bail(st);
+  if ((st = cp(c->d.seg_off, seg_off.data(), seg_off.size() * sizeof(int32_t)))) return bail(st);
+  if ((st = cp(c->d.seg_base, seg_base.data(), seg_base.size() * sizeof(int32_t)))) return bail(st);
+  if ((st = cp(c->d.seg_delta, seg_delta.data(), seg_delta.size()))) return bail(st);
   if ((st = cp(c->d.order, c->order_host.data(), np * sizeof(int32_t)))) return bail(st);
   if (!corr.empty() && (st = cp(c->d.corr, corr.data(), corr.size() * sizeof(double)))) return bail(st);
   if ((st = upload_tables(c))) return bail(st);
-  pull.clear();
-  pull.shrink_to_fit();
   if ((st = hlb_init_equilibrium(c, nullptr, nullptr, 0))) return bail(st);
   *out = c;
   return HLB_OK;
@@ -610,7 +657,7 @@ hlb_status hlb_step(hlb_ctx *c, int64_t n) {
   if (n < 0) return fail(HLB_EINVAL, "n < 0");
   if (hlb_status st = bind(c)) return st;
   for (int64_t s = 0; s < n; ++s) {
-    hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
     if (c->timing) {
       if (c->n_timed == c->pool.size()) {
         TimedStep ts;
@@ -620,9 +667,8 @@ hlb_status hlb_step(hlb_ctx *c, int64_t n) {
       TimedStep &ts = c->pool[c->n_timed++];
       e0 = ts.e[0];
       e1 = ts.e[1];
-      e2 = ts.e[2];
     }
-    HIP_TRY(launch_step(c->cfg, c->L, c->d, c->cur, c->t, c->stream, e0, e1, e2));
+    HIP_TRY(launch_step(c->cfg, c->L, c->d, c->cur, c->t, c->stream, e0, e1));
     c->cur = 1 - c->cur;
     c->direct = false;
     c->t += 1;
@@ -717,8 +763,11 @@ hlb_status hlb_info(const hlb_ctx *c, hlb_info_t *info) {
   for (int g = 0; g < kGroups; ++g) info->group_sites[g] = c->L.gcnt[g];
   info->storage = c->cfg.storage;
   info->order = c->order;
-  // 19 loads + 19 stores of the populations and 18 int32 pull entries per site update
-  info->bytes_per_lup = 38.0 * (double)storage_bytes(c->cfg.storage) + 18.0 * 4.0;
+  // 19 loads + 19 stores of the populations, plus the pull tables (read once
+  // per step), per site update
+  info->table_bytes_per_site = (double)c->table_bytes / (double)c->L.n_sites;
+  info->bytes_per_lup = 38.0 * (double)storage_bytes(c->cfg.storage) + info->table_bytes_per_site;
+  info->n_segments = c->L.nseg;
   info->device_bytes = c->dev_bytes;
   return HLB_OK;
 }
@@ -730,7 +779,7 @@ hlb_status hlb_set_timing(hlb_ctx *c, int32_t enable) {
   c->timing = enable != 0;
   c->n_timed = 0;
   c->steps_timed = 0;
-  c->sum_bulk = c->sum_io = c->sum_step = 0.0;
+  c->sum_kernel = c->sum_step = 0.0;
   return HLB_OK;
 }
 
@@ -741,22 +790,19 @@ hlb_status hlb_stats(hlb_ctx *c, hlb_stats_t *s) {
   HIP_TRY(hipStreamSynchronize(c->stream));
   if (c->n_timed > 0) {
     for (size_t k = 0; k < c->n_timed; ++k) {
-      float a = 0, b = 0;
+      float a = 0;
       HIP_TRY(hipEventElapsedTime(&a, c->pool[k].e[0], c->pool[k].e[1]));
-      HIP_TRY(hipEventElapsedTime(&b, c->pool[k].e[1], c->pool[k].e[2]));
-      c->sum_bulk += a;
-      c->sum_io += b;
+      c->sum_kernel += a;
     }
     float whole = 0;
-    HIP_TRY(hipEventElapsedTime(&whole, c->pool[0].e[0], c->pool[c->n_timed - 1].e[2]));
+    HIP_TRY(hipEventElapsedTime(&whole, c->pool[0].e[0], c->pool[c->n_timed - 1].e[1]));
     c->sum_step += whole;
     c->steps_timed += (int64_t)c->n_timed;
     c->n_timed = 0;
   }
   s->steps = c->steps_timed;
   const double k = c->steps_timed > 0 ? (double)c->steps_timed : 1.0;
-  s->bulk_kernel_ms = c->sum_bulk / k;
-  s->iolet_kernel_ms = c->sum_io / k;
+  s->kernel_ms = c->sum_kernel / k;
   s->step_ms = c->sum_step / k;
   return HLB_OK;
 }

@@ -49,12 +49,12 @@ class hlb_options(ctypes.Structure):
 class hlb_info_t(ctypes.Structure):
     _fields_ = [("n_sites", ctypes.c_int64), ("n_padded", ctypes.c_int64), ("group_sites", ctypes.c_int64 * 6),
                 ("storage", ctypes.c_int32), ("order", ctypes.c_int32), ("bytes_per_lup", ctypes.c_double),
-                ("device_bytes", ctypes.c_int64)]
+                ("device_bytes", ctypes.c_int64), ("table_bytes_per_site", ctypes.c_double),
+                ("n_segments", ctypes.c_int64)]
 
 
 class hlb_stats_t(ctypes.Structure):
-    _fields_ = [("steps", ctypes.c_int64), ("bulk_kernel_ms", ctypes.c_double),
-                ("iolet_kernel_ms", ctypes.c_double), ("step_ms", ctypes.c_double)]
+    _fields_ = [("steps", ctypes.c_int64), ("kernel_ms", ctypes.c_double), ("step_ms", ctypes.c_double)]
 
 
 _P = ctypes.c_void_p
@@ -89,6 +89,7 @@ _SIGS = {
     "hlb_state_save": [_P, _P],
     "hlb_state_load": [_P, _P],
     "hlb_sync": [_P],
+    "hlb_copy_bandwidth": [_i64, _i32, ctypes.POINTER(_d)],
     "hlb_last_error": [],
 }
 EXPORTED = tuple(_SIGS)
@@ -221,7 +222,8 @@ def hlb_info(ctx) -> dict:
     i = hlb_info_t()
     _check(load().hlb_info(ctx, ctypes.byref(i)), "hlb_info")
     return dict(n_sites=i.n_sites, n_padded=i.n_padded, group_sites=list(i.group_sites)[:5], storage=i.storage,
-                order=i.order, bytes_per_lup=i.bytes_per_lup, device_bytes=i.device_bytes)
+                order=i.order, bytes_per_lup=i.bytes_per_lup, device_bytes=i.device_bytes,
+                table_bytes_per_site=i.table_bytes_per_site, n_segments=i.n_segments)
 
 
 def hlb_macros(ctx, want=("rho", "u", "wss")):
@@ -270,7 +272,7 @@ def hlb_set_timing(ctx, enable: bool):
 def hlb_stats(ctx) -> dict:
     s = hlb_stats_t()
     _check(load().hlb_stats(ctx, ctypes.byref(s)), "hlb_stats")
-    return dict(steps=s.steps, bulk_kernel_ms=s.bulk_kernel_ms, iolet_kernel_ms=s.iolet_kernel_ms, step_ms=s.step_ms)
+    return dict(steps=s.steps, kernel_ms=s.kernel_ms, step_ms=s.step_ms)
 
 
 def hlb_snapshot_alloc(ctx, n_slots: int):
@@ -308,6 +310,12 @@ def hlb_sync(ctx):
     _check(load().hlb_sync(ctx), "hlb_sync")
 
 
+def hlb_copy_bandwidth(nbytes: int = 4 << 30, reps: int = 20) -> float:
+    g = ctypes.c_double()
+    _check(load().hlb_copy_bandwidth(int(nbytes), int(reps), ctypes.byref(g)), "hlb_copy_bandwidth")
+    return g.value
+
+
 # ---------------------------------------------------------------------------
 
 @dataclass
@@ -319,12 +327,12 @@ class Simulation:
     n: int
 
     @classmethod
-    def create(cls, geom, tau: float, storage: str = "f64", order: str = "brick", xcd_remap: bool = True,
+    def create(cls, geom, tau: float, storage: str = "f64", order: str = "lex", xcd_remap: int = 2,
                rho0: float = 1.0, max_device_bytes: int = 0, tables=None):
         opt = hlb_default_options()
         opt.storage = STORAGE[storage]
         opt.order = ORDER[order]
-        opt.xcd_remap = 1 if xcd_remap else 0
+        opt.xcd_remap = int(xcd_remap)
         opt.rho0 = float(rho0)
         opt.max_device_bytes = int(max_device_bytes)
         ctx = hlb_create(geom.coords, geom.types, geom.nbr, tau, geom.iolets, opt)

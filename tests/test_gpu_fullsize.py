@@ -1,7 +1,7 @@
 """Parity at the benchmark's full size and launch configuration.
 
 The 2.0e7-site tree of the benchmark (seed 2, 8 generations, tau 0.6, one
-Ladd inlet, 256 pressure outlets), brick order, XCD remap, FP64: a few steps
+Ladd inlet, 256 pressure outlets), default order and launch, FP64: a few steps
 from the inlet-amplitude peak, every site compared against the oracle.
 """
 import sys
@@ -30,7 +30,7 @@ def tree20m():
 def test_tree_20m_fp64_parity(tree20m):
     g, tables = tree20m
     t0, steps, tau = 1000, 6, 0.6  # start at the inlet amplitude's peak
-    print(f"case: tree {g.n} sites, t0 {t0}, {steps} steps, f64, brick+xcd", flush=True)
+    print(f"case: tree {g.n} sites, t0 {t0}, {steps} steps, f64, default launch", flush=True)
     sim = hlb.Simulation.create(g, tau, tables=tables)
     hlb.hlb_init_equilibrium(sim.ctx, None, None, t0)
     sim.step(steps)
