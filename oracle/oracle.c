@@ -77,16 +77,16 @@ void orc_init(int64_t n, const double *rho, const double *u, double rho0, double
   }
 }
 
-static double table_at(const orc_iolet *k, int64_t s) {
+double orc_table_at(const orc_iolet *k, int64_t s) {
   if (k->table == NULL || k->table_len <= 0) return k->kind == 0 ? 0.0 : 1.0;
   return k->table[s % k->table_len];
 }
 
-/* Velocity imposed by a Ladd iolet at point m (Sec. 2.3.2): the amplitude
- * A_k(s) times a positional weight, along the iolet's velocity direction.
+/* Velocity profile of a Ladd iolet at point m per unit amplitude (Sec.
+ * 2.3.2): a positional weight along the iolet's velocity direction.
  * Weight: parabolic in the distance d of m from the iolet axis,
  * max(0, 1 - d^2/R^2); uniform when R <= 0. */
-static void iolet_velocity(const orc_iolet *k, const double *m, int64_t s, double *U) {
+void orc_iolet_profile(const orc_iolet *k, const double *m, double *P) {
   double wgt = 1.0;
   if (k->radius > 0.0) {
     const double r[3] = {m[0] - k->centre[0], m[1] - k->centre[1], m[2] - k->centre[2]};
@@ -97,10 +97,19 @@ static void iolet_velocity(const orc_iolet *k, const double *m, int64_t s, doubl
   }
   const double *v = k->vdir;
   if (v[0] == 0.0 && v[1] == 0.0 && v[2] == 0.0) v = k->normal;
-  const double a = table_at(k, s) * wgt;
-  U[0] = a * v[0];
-  U[1] = a * v[1];
-  U[2] = a * v[2];
+  P[0] = wgt * v[0];
+  P[1] = wgt * v[1];
+  P[2] = wgt * v[2];
+}
+
+/* Velocity imposed at m and step s: the amplitude A_k(s) times the profile. */
+static void iolet_velocity(const orc_iolet *k, const double *m, int64_t s, double *U) {
+  double P[3];
+  orc_iolet_profile(k, m, P);
+  const double a = orc_table_at(k, s);
+  U[0] = a * P[0];
+  U[1] = a * P[1];
+  U[2] = a * P[2];
 }
 
 /* Compensated (Kahan) accumulator. */
@@ -173,7 +182,7 @@ int orc_step(int64_t n, const int32_t *coords, const int32_t *nbr, double tau, d
             const double un = u[0] * nk[0] + u[1] * nk[1] + u[2] * nk[2];
             const double ug[3] = {un * nk[0], un * nk[1], un * nk[2]};
             double fg[ORC_Q];
-            orc_equilibrium(table_at(K, t), ug, fg);
+            orc_equilibrium(orc_table_at(K, t), ug, fg);
             val = fg[OPP[i]];
           }
           kadd(&acc, val - fp[i]);

@@ -89,6 +89,25 @@ void orc_macros(int64_t n, const int32_t *nbr, double tau, const double *f, doub
 /* Total mass sum_x sum_i f_i (compensated summation). */
 double orc_mass(int64_t n, const double *f);
 
+/* Table value of iolet k at step s (table[s mod len]). */
+double orc_table_at(const orc_iolet *k, int64_t s);
+/* Ladd velocity profile per unit amplitude at point m: weight times direction. */
+void orc_iolet_profile(const orc_iolet *k, const double *m, double *P);
+
+/* Reference adjoint (oracle_adjoint.c).  Objective
+ *   J = sum over t in (obj_t0, obj_t1], t0 < t <= t0 + nsteps, of the sum of
+ *       WSS(x, t) over the sites with wall links,
+ * WSS of the pre-collision state at t as in orc_macros.  From the state f0
+ * at t0, run nsteps forward (storing every state), then the adjoint sweep.
+ * Outputs: *J; dJ_dA [n_io][nsteps]: derivative with respect to the table
+ * value iolet k uses at step t0+s (velocity iolets; zero for pressure ones);
+ * dJ_dphi [n]: derivative with respect to each site's porosity (zero at sites
+ * without wall links).  phi may be NULL (no porosity, derivative still at
+ * phi = 0).  Returns 0, or -1 on a bad link code / allocation failure. */
+int orc_adj_run(int64_t n, const int32_t *coords, const int32_t *nbr, double tau, double rho0,
+                const orc_iolet *io, int32_t n_io, const double *phi, int64_t t0, int64_t nsteps,
+                int64_t obj_t0, int64_t obj_t1, const double *f0, double *J, double *dJ_dA, double *dJ_dphi);
+
 /* Number of OpenMP threads the oracle uses. */
 int32_t orc_threads(void);
 
