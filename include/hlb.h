@@ -117,7 +117,8 @@ typedef struct {
   int32_t xcd_remap;   /* K > 0: renumber the bulk kernel's workgroups so that
                           each of the 8 XCDs gets K consecutive tiles of every
                           window of 8K tiles (default 2); 0: plain block order */
-  int32_t reserved;    /* must be 0 */
+  int32_t adjoint;     /* 1: also build the tables of hlb_adjoint_run (FP64
+                          storage only; 72 more bytes per site); default 0 */
   double rho0;         /* reference density (default 1.0) */
   int64_t max_device_bytes; /* 0: no limit; otherwise HLB_ENOMEM above it */
 } hlb_options;
@@ -211,6 +212,9 @@ typedef struct {
   int64_t device_bytes;     /* device memory held by the context */
   double table_bytes_per_site; /* neighbour-table bytes read per site update */
   int64_t n_segments;       /* segments of the bulk+wall group's table */
+  int64_t n_iolets;         /* iolets given to hlb_create */
+  int32_t adjoint;          /* adjoint tables built (opt.adjoint) */
+  int32_t porous;           /* a porosity field is set */
 } hlb_info_t;
 hlb_status hlb_info(const hlb_ctx *ctx, hlb_info_t *info);
 
@@ -225,6 +229,27 @@ typedef struct {
   double step_ms;    /* mean stream time per step, first to last timed event */
 } hlb_stats_t;
 hlb_status hlb_stats(hlb_ctx *ctx, hlb_stats_t *stats);
+
+/* Differentiation (not a rule of the paper): the adjoint of the update.
+ * From the current state at time t0, run n >= 1 steps and the reverse-time
+ * sweep for the objective
+ *   J = sum over t in (obj_t0, obj_t1], t0 < t <= t0 + n, of the wall shear
+ *       stress (hlb_macros' definition) summed over the sites with wall links,
+ * with respect to
+ *   dJ_dA   [n_iolets][n] (host, may be NULL): the table value A_k(t0 + s)
+ *           that velocity iolet k uses in the update t0+s -> t0+s+1
+ *           (zero rows for pressure iolets);
+ *   dJ_dphi [n_sites] (host, caller order, may be NULL): each site's
+ *           porosity (hlb_set_porosity), zero at sites without wall links,
+ *           evaluated at the current porosity (0 if none is set).
+ * The forward states are recomputed from n_snap device snapshots
+ * (1 <= n_snap <= 4096; binomial checkpointing after Griewank & Walther's
+ * revolve): with n <= C(n_snap - 1 + r, r) the forward sweep is repeated at
+ * most r times.  *forward_steps (may be NULL) receives the forward steps
+ * run.  The state is left as it was (time t0).  Needs opt.adjoint at
+ * creation and FP64 storage (HLB_ESTATE otherwise). */
+hlb_status hlb_adjoint_run(hlb_ctx *ctx, int64_t n, int64_t obj_t0, int64_t obj_t1, int32_t n_snap,
+                           double *J, double *dJ_dA, double *dJ_dphi, int64_t *forward_steps);
 
 /* Device snapshots of the whole state (for checkpointing schedules).
  * hlb_snapshot_alloc reserves n_slots slots (frees previous ones). */

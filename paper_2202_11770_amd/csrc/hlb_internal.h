@@ -90,6 +90,22 @@ hipError_t launch_macros(const LaunchCfg &cfg, const Layout &L, const DevPtrs &d
 // buffer `pre` := f - w rho0, buffer 1-pre := its collision.
 hipError_t launch_set_state(const LaunchCfg &cfg, const Layout &L, const DevPtrs &d, int pre,
                             const double *staging, hipStream_t s);
+// Device buffers of the adjoint sweep (FP64 storage only).
+struct AdjBuffers {
+  double *mu = nullptr;       // [19][np] adjoint of the post-collision state
+  double *nu = nullptr;       // [19][np] adjoint of the pre-collision state
+  int32_t *push = nullptr;    // [18][np] position of x + c_i, or the link code
+  double *J = nullptr;        // objective accumulator
+  double *dA = nullptr;       // [n_iolets][n_steps]
+  double *dphi = nullptr;     // [np] porosity derivative per position
+};
+// Adjoint of the update (t-1 -> t): buffer `src` holds s_{t-1}; b.mu holds
+// mu_t on entry and mu_{t-1} on return; accumulates J (if in_window), the
+// Ladd amplitude derivatives into column `step` of dA and the porosity
+// derivatives.
+hipError_t launch_adjoint_step(const LaunchCfg &cfg, const Layout &L, const DevPtrs &d, int src, int64_t t,
+                               const AdjBuffers &b, int in_window, int64_t n_steps, int64_t step,
+                               hipStream_t s);
 // p[0..n) := 0 (a kernel, so that no memset node lands in a captured graph).
 hipError_t launch_zero(double *p, int64_t n, hipStream_t s);
 // Sum of the stored deviations of buffer `src` into d.partial[0] (FP64).

@@ -20,242 +20,12 @@
 // The method is bound by HBM bandwidth (~0.7 flop per byte in FP64), so
 // nothing here uses the matrix cores.
 
-#include <type_traits>
-
-#include "hlb_internal.h"
+#include "hlb_device.h"
 
 namespace hlb {
 namespace {
 
-constexpr int Q = 19;
-constexpr int kBlock = 256;
-
-// D3Q19, opposite directions adjacent (the input convention of hlb.h).
-__host__ __device__ constexpr int cx(int i) {
-  constexpr int v[Q] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
-  return v[i];
-}
-__host__ __device__ constexpr int cy(int i) {
-  constexpr int v[Q] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
-  return v[i];
-}
-__host__ __device__ constexpr int cz(int i) {
-  constexpr int v[Q] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
-  return v[i];
-}
-__host__ __device__ constexpr int opp(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
-// weights 1/3, 1/18, 1/36 (Sec. 2.2)
-template <typename C>
-__host__ __device__ constexpr C wgt(int i) {
-  return i == 0 ? C(1) / C(3) : (i <= 6 ? C(1) / C(18) : C(1) / C(36));
-}
-
-// Compute type: double for FP64 storage, float for the shifted FP32/FP16 forms.
-template <typename T>
-struct Acc { using type = float; };
-template <>
-struct Acc<double> { using type = double; };
-// Stored value s_i = f_i - shift_i, shift_i = w_i rho0 for the shifted forms
-// and 0 for FP64; rest_i is the stored value of the rest state.
-template <typename T>
-constexpr bool kShifted = !std::is_same<T, double>::value;
-template <bool SH, typename C>
-__device__ inline C shift(int i, C rho0) {
-  return SH ? wgt<C>(i) * rho0 : C(0);
-}
-template <bool SH, typename C>
-__device__ inline C rest(int i, C rho0) {
-  return SH ? C(0) : wgt<C>(i) * rho0;
-}
-
-__device__ inline double ld(const double *p) { return *p; }
-__device__ inline float ld(const float *p) { return *p; }
-__device__ inline float ld(const _Float16 *p) { return static_cast<float>(*p); }
-// Population stores and pull-table loads stream through HBM once per step:
-// non-temporal, so that they do not displace the gathered lines from cache.
-__device__ inline void st(double *p, double v) { __builtin_nontemporal_store(v, p); }
-__device__ inline void st(float *p, float v) { __builtin_nontemporal_store(v, p); }
-__device__ inline void st(_Float16 *p, float v) {
-  __builtin_nontemporal_store(static_cast<_Float16>(v), p);  // round to nearest even
-}
-__device__ inline uint8_t ld_stream(const uint8_t *p) { return __builtin_nontemporal_load(p); }
-
-// Workgroups are dealt to the 8 XCDs round-robin by block id.  With a chunk
-// size K > 0 the blocks are renumbered so that each XCD gets K consecutive
-// tiles of every window of 8K tiles: neighbouring tiles then share that
-// XCD's L2 while the chip as a whole still sweeps the site list in order.
-// The last, partial window keeps the plain order.
-__device__ inline int64_t block_id(int64_t b, int64_t G, int chunk) {
-  if (chunk <= 0) return b;
-  const int64_t win = 8 * (int64_t)chunk;
-  const int64_t w = b / win;
-  if ((w + 1) * win > G) return b;
-  const int64_t r = b - w * win;
-  return w * win + (r & 7) * chunk + (r >> 3);
-}
-
-__device__ inline double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
-
-// Moments (eqs. (5), (6)) of stored values s: rho = sum f, j = sum f c.
-// Sums run in ascending i.  For the shifted forms rho = rho0 + sum s.
-template <bool SH, typename C>
-__device__ inline void moments(const C (&s)[Q], C rho0, C &dr, C &rho, C &jx, C &jy, C &jz) {
-  dr = 0;
-  jx = 0;
-  jy = 0;
-  jz = 0;
-#pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    dr += s[i];
-    if (cx(i)) jx += cx(i) > 0 ? s[i] : -s[i];
-    if (cy(i)) jy += cy(i) > 0 ? s[i] : -s[i];
-    if (cz(i)) jz += cz(i) > 0 ? s[i] : -s[i];
-  }
-  rho = SH ? rho0 + dr : dr;
-}
-
-// Equilibrium eq. (4) (1/2 factors on the second-order terms) in the stored
-// representation:  f_eq = w rho (1 + 3 c.u + 9/2 (c.u)^2 - 3/2 u.u);
-// shifted: f_eq - w rho0 = w ((rho - rho0) + rho (3 c.u + 9/2 (c.u)^2 - 3/2 u.u)).
-template <bool SH, typename C>
-__device__ inline C s_eq(int i, C rho, C rho0, C ux, C uy, C uz, C usq15) {
-  const C cu = C(cx(i)) * ux + C(cy(i)) * uy + C(cz(i)) * uz;
-  const C q = C(3) * cu + C(4.5) * cu * cu - usq15;
-  return SH ? wgt<C>(i) * ((rho - rho0) + rho * q) : wgt<C>(i) * rho * (C(1) + q);
-}
-
-// BGK collision, eq. (3a) with dt = 1: s' = s + omega (s_eq - s).
-template <bool SH, typename C>
-__device__ inline void collide(C (&s)[Q], C omega, C rho0) {
-  C dr, rho, jx, jy, jz;
-  moments<SH>(s, rho0, dr, rho, jx, jy, jz);
-  const C inv = C(1) / rho;
-  const C ux = jx * inv, uy = jy * inv, uz = jz * inv;
-  const C usq = C(1.5) * (ux * ux + uy * uy + uz * uz);
-#pragma unroll
-  for (int i = 0; i < Q; ++i) s[i] = s[i] + omega * (s_eq<SH>(i, rho, rho0, ux, uy, uz, usq) - s[i]);
-}
-
-struct GatherArgs {
-  const int32_t *seg_off;     // bulk+wall group: per-segment source offsets
-  const int32_t *seg_base;
-  const uint8_t *seg_delta;
-  const int32_t *nbr_io;      // iolet groups: [18][nio] sources / link codes
-  int64_t np;
-  int64_t io_begin;
-  int64_t nio;
-  const double *corr;
-  const IoletDev *io;
-  const double *tables;
-  int64_t t;           // the update t -> t+1 uses the tables at t
-  const double *phi;   // porosity or null
-  double rho0;
-};
-
-static_assert(kBlock == kSegBlock, "one segment base per workgroup");
-static_assert(kSegRow == 20, "segment rows are five 16-byte vectors");
-
-// Source offsets of the 18 incoming links of bulk+wall position p, whose
-// kSegBlock-position block is blk: off[i-1] = source - p, the source being
-// a fluid position in [0, np) or, for a wall link, the site's own slot of
-// direction opp(i) (offset +-np, outside [0, np)).
-__device__ inline void bulk_offsets(const GatherArgs &a, int64_t p, int64_t blk, int32_t (&off)[Q - 1]) {
-  const int32_t s = a.seg_base[blk] + (int32_t)ld_stream(a.seg_delta + p);
-  const int4 *row = reinterpret_cast<const int4 *>(a.seg_off + (int64_t)s * kSegRow);
-  int4 r[5];
-#pragma unroll
-  for (int k = 0; k < 5; ++k) r[k] = row[k];
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    off[4 * k] = r[k].x;
-    off[4 * k + 1] = r[k].y;
-    off[4 * k + 2] = r[k].z;
-    off[4 * k + 3] = r[k].w;
-  }
-  off[16] = r[4].x;
-  off[17] = r[4].y;
-}
-
-// Pre-collision populations of site p at time t+1, gathered from the
-// post-collision buffer A of time t (stored values s = f - off), with the
-// boundary rules (Sec. 2.3) for links that do not reach a fluid site:
-//   wall (mid-link bounce-back):  f_i = f'_opp(i)(p); a porous wall site
-//                                 returns (1 - phi) f'_opp(i) + phi w_i rho0
-//   velocity iolet (Ladd):        f_i = f'_opp(i)(p) + 6 w_i rho0 (c_i.U(m)),
-//                                 m = x - c_i/2, U = A_k(t) W(m) v_k
-//   pressure iolet (ghost rho):   f_i = f_i^eq(rho_k(t), (u.n) n),
-//                                 u the site's velocity at time t
-// Returns the mass the boundary rules added (filled - reflected).
-// IOLET = false: the site has only fluid and wall links.
-// blk: the kSegBlock-position block of p (bulk+wall group only).
-template <bool IOLET, bool POROUS, bool SH, typename T, typename C>
-__device__ inline C gather(const T *__restrict__ A, int64_t p, int64_t blk, const GatherArgs &a, C (&g)[Q]) {
-  const int64_t np = a.np;
-  C flux = 0;
-  if constexpr (!IOLET) {
-    // Bulk+wall group: every link, bounce-back included, is a plain load at
-    // p + off from direction array i; the offsets are fetched before the
-    // 18 gathers are issued.
-    int32_t off[Q - 1];
-    bulk_offsets(a, p, blk, off);
-    g[0] = ld(A + p);
-#pragma unroll
-    for (int i = 1; i < Q; ++i) {
-      const int64_t j = p + (int64_t)off[i - 1];
-      C v = ld(A + (int64_t)i * np + j);
-      if constexpr (POROUS) {
-        if ((uint64_t)j >= (uint64_t)np) {
-          const C nv = v - C(a.phi[p]) * (v - rest<SH, C>(i, C(a.rho0)));
-          flux += nv - v;
-          v = nv;
-        }
-      }
-      g[i] = v;
-    }
-  } else {
-    C own[Q];
-#pragma unroll
-    for (int i = 0; i < Q; ++i) own[i] = ld(A + (int64_t)i * np + p);
-    // velocity at time t: moments of the site's own post-collision state
-    // (the collision conserves rho and rho u)
-    C dr, rho, jx, jy, jz;
-    moments<SH>(own, C(a.rho0), dr, rho, jx, jy, jz);
-    const C ux = jx / rho, uy = jy / rho, uz = jz / rho;
-    g[0] = own[0];
-#pragma unroll
-    for (int i = 1; i < Q; ++i) {
-      const int32_t code = a.nbr_io[(int64_t)(i - 1) * a.nio + (p - a.io_begin)];
-      if (code >= 0) {
-        g[i] = ld(A + (int64_t)i * np + code);
-        continue;
-      }
-      const C back = own[opp(i)];
-      C v;
-      if (code == HLB_LINK_WALL) {
-        v = back;
-        if constexpr (POROUS) v = back - C(a.phi[p]) * (back - rest<SH, C>(i, C(a.rho0)));
-      } else {
-        const IoletDev K = a.io[-code - 2];
-        const double val = a.tables[K.tab_off + a.t % K.tab_len];
-        if (K.kind == HLB_IOLET_VELOCITY) {
-          v = back + C(a.corr[(int64_t)(i - 1) * a.nio + (p - a.io_begin)] * val);
-        } else {
-          const C un = ux * C(K.n[0]) + uy * C(K.n[1]) + uz * C(K.n[2]);
-          const C gx = un * C(K.n[0]), gy = un * C(K.n[1]), gz = un * C(K.n[2]);
-          const C uu = C(1.5) * (gx * gx + gy * gy + gz * gz);
-          v = s_eq<SH>(i, C(val), C(a.rho0), gx, gy, gz, uu);
-        }
-      }
-      flux += v - back;
-      g[i] = v;
-    }
-  }
-  return flux;
-}
+using namespace dev;
 
 // ---------------------------------------------------------------- step ----
 
@@ -483,24 +253,6 @@ __global__ __launch_bounds__(kBlock) void k_mass_final(double *partial, int64_t 
 __global__ void k_zero(double *p, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0.0;
-}
-
-GatherArgs make_args(const LaunchCfg &cfg, const Layout &L, const DevPtrs &d, int64_t t) {
-  GatherArgs a;
-  a.seg_off = d.seg_off;
-  a.seg_base = d.seg_base;
-  a.seg_delta = d.seg_delta;
-  a.nbr_io = d.nbr_io;
-  a.np = L.np;
-  a.io_begin = L.io_begin;
-  a.nio = L.nio;
-  a.corr = d.corr;
-  a.io = d.io;
-  a.tables = d.tables;
-  a.t = t;
-  a.phi = cfg.porous ? d.phi : nullptr;
-  a.rho0 = cfg.rho0;
-  return a;
 }
 
 inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }

@@ -155,6 +155,10 @@ struct hlb_ctx {
     bool valid = false;
   };
   std::vector<Snap> snaps;
+  // adjoint
+  AdjBuffers adj;
+  int64_t adj_dA_len = 0;
+  std::vector<void *> adj_slots;  // checkpoint buffers (post-collision state)
 };
 
 namespace {
@@ -181,6 +185,10 @@ void free_all(hlb_ctx *c) {
   F(c->d.phi); F(c->d.acc); F(c->d.partial); F(c->d.io_scratch);
   for (auto &s : c->snaps) { F(s.f[0]); F(s.f[1]); F(s.acc); }
   c->snaps.clear();
+  F(c->adj.mu); F(c->adj.nu); F(c->adj.push); F(c->adj.J); F(c->adj.dA); F(c->adj.dphi);
+  for (void *q : c->adj_slots) F(q);
+  c->adj_slots.clear();
+  c->adj = AdjBuffers();
   for (auto &ts : c->pool)
     for (auto &e : ts.e) (void)hipEventDestroy(e);
   c->pool.clear();
@@ -281,7 +289,7 @@ hlb_status hlb_default_options(hlb_options *opt) {
   opt->storage = HLB_F64;
   opt->order = HLB_ORDER_LEX;
   opt->xcd_remap = 2;
-  opt->reserved = 0;
+  opt->adjoint = 0;
   opt->rho0 = 1.0;
   opt->max_device_bytes = 0;
   return HLB_OK;
@@ -302,8 +310,10 @@ hlb_status hlb_create(int64_t n, const int32_t *coords, const uint8_t *type, con
   if (opt.storage < HLB_F64 || opt.storage > HLB_F16_SHIFTED) return fail(HLB_EINVAL, "bad storage %d", opt.storage);
   if (opt.order < HLB_ORDER_INPUT || opt.order > HLB_ORDER_BRICK) return fail(HLB_EINVAL, "bad order %d", opt.order);
   if (!(opt.rho0 > 0.0) || !std::isfinite(opt.rho0)) return fail(HLB_EINVAL, "rho0 must be finite and > 0");
-  if (opt.reserved != 0 || opt.max_device_bytes < 0 || opt.xcd_remap < 0 || opt.xcd_remap > (1 << 20))
+  if ((opt.adjoint != 0 && opt.adjoint != 1) || opt.max_device_bytes < 0 || opt.xcd_remap < 0 ||
+      opt.xcd_remap > (1 << 20))
     return fail(HLB_EINVAL, "bad options");
+  if (opt.adjoint && opt.storage != HLB_F64) return fail(HLB_EINVAL, "the adjoint needs FP64 storage");
   for (int k = 0; k < n_iolets; ++k) {
     const hlb_iolet &I = iolets[k];
     if (I.kind != HLB_IOLET_VELOCITY && I.kind != HLB_IOLET_PRESSURE) return fail(HLB_EINVAL, "iolet %d: bad kind", k);
@@ -469,6 +479,20 @@ hlb_status hlb_create(int64_t n, const int32_t *coords, const uint8_t *type, con
   for (int64_t p = 0; p < n0; ++p) seg_delta[p] = (uint8_t)(segid[p] - segid[(p / kSegBlock) * kSegBlock]);
   segid.clear();
   segid.shrink_to_fit();
+  // ---- adjoint: push table, position of x + c_i or the link code ----
+  std::vector<int32_t> push;
+  if (opt.adjoint) {
+    push.assign((size_t)18 * np, HLB_LINK_WALL);
+#pragma omp parallel for schedule(static)
+    for (int64_t p = 0; p < np; ++p) {
+      const int32_t x = c->order_host[p];
+      if (x < 0) continue;
+      for (int i = 1; i < Q; ++i) {
+        const int32_t y = nbr[Q * (int64_t)x + i];
+        push[(size_t)(i - 1) * np + p] = y >= 0 ? inv[y] : y;
+      }
+    }
+  }
   // ---- Ladd coefficients 6 w_i rho0 (c_i . v_k) W_k(x - c_i/2) of velocity-iolet links ----
   std::vector<double> corr((size_t)18 * L.nio, 0.0);
 #pragma omp parallel for schedule(static)
@@ -561,6 +585,11 @@ hlb_status hlb_create(int64_t n, const int32_t *coords, const uint8_t *type, con
   if ((st = cp(c->d.seg_off, seg_off.data(), seg_off.size() * sizeof(int32_t)))) return bail(st);
   if ((st = cp(c->d.seg_base, seg_base.data(), seg_base.size() * sizeof(int32_t)))) return bail(st);
   if ((st = cp(c->d.seg_delta, seg_delta.data(), seg_delta.size()))) return bail(st);
+  if (!push.empty()) {
+    if ((st = dev_alloc(c, &p, push.size() * sizeof(int32_t)))) return bail(st);
+    c->adj.push = static_cast<int32_t *>(p);
+    if ((st = cp(c->adj.push, push.data(), push.size() * sizeof(int32_t)))) return bail(st);
+  }
   if ((st = cp(c->d.order, c->order_host.data(), np * sizeof(int32_t)))) return bail(st);
   if (!corr.empty() && (st = cp(c->d.corr, corr.data(), corr.size() * sizeof(double)))) return bail(st);
   if ((st = upload_tables(c))) return bail(st);
@@ -768,6 +797,9 @@ hlb_status hlb_info(const hlb_ctx *c, hlb_info_t *info) {
   info->table_bytes_per_site = (double)c->table_bytes / (double)c->L.n_sites;
   info->bytes_per_lup = 38.0 * (double)storage_bytes(c->cfg.storage) + info->table_bytes_per_site;
   info->n_segments = c->L.nseg;
+  info->n_iolets = (int64_t)c->iolets.size();
+  info->adjoint = c->adj.push ? 1 : 0;
+  info->porous = c->cfg.porous ? 1 : 0;
   info->device_bytes = c->dev_bytes;
   return HLB_OK;
 }
@@ -913,3 +945,166 @@ hlb_status hlb_sync(hlb_ctx *c) {
 }
 
 }  // extern "C"
+
+namespace {
+
+// C(n, k), saturating at 2^62.
+int64_t binom_sat(int64_t n, int64_t k) {
+  if (k < 0 || k > n) return 0;
+  if (k > n - k) k = n - k;
+  long double v = 1.0L;
+  for (int64_t i = 1; i <= k; ++i) {
+    v = v * (long double)(n - k + i) / (long double)i;
+    if (v > 4.6e18L) return (int64_t)1 << 62;
+  }
+  return (int64_t)(v + 0.5L);
+}
+
+// Reverse sweep with binomial checkpointing (Griewank & Walther's revolve
+// schedule, written as a recursion): the state at time a is in slot
+// `slot_a`, `cfree` more slots are free; adjoint steps b, b-1, ..., a+1 are
+// run, each with the forward state of the preceding time restored or
+// recomputed.  With l = b - a steps and r the least integer with
+// C(cfree + r, cfree) >= l, a checkpoint is placed so that the part after it
+// fits C(cfree - 1 + r, cfree - 1) steps.
+struct Revolve {
+  hlb_ctx *c;
+  int64_t t0, n, w0, w1, n_snap;
+  std::vector<int64_t> slot_t;
+  int64_t fwd = 0;
+
+  hlb_status advance(int64_t k) {
+    for (int64_t s = 0; s < k; ++s) {
+      HIP_TRY(launch_step(c->cfg, c->L, c->d, c->cur, c->t, c->stream, nullptr, nullptr));
+      c->cur = 1 - c->cur;
+      c->t += 1;
+    }
+    fwd += k;
+    return HLB_OK;
+  }
+  hlb_status save(int64_t slot) {
+    HIP_TRY(hipMemcpyAsync(c->adj_slots[slot], c->d.f[c->cur], buf_bytes(c), hipMemcpyDeviceToDevice, c->stream));
+    slot_t[slot] = c->t;
+    return HLB_OK;
+  }
+  hlb_status restore(int64_t slot) {
+    HIP_TRY(hipMemcpyAsync(c->d.f[0], c->adj_slots[slot], buf_bytes(c), hipMemcpyDeviceToDevice, c->stream));
+    c->cur = 0;
+    c->t = slot_t[slot];
+    c->direct = false;
+    return HLB_OK;
+  }
+  hlb_status adjoint_step(int64_t t) {  // needs the state of time t-1
+    const int in_window = (t > w0 && t <= w1) ? 1 : 0;
+    HIP_TRY(launch_adjoint_step(c->cfg, c->L, c->d, c->cur, t, c->adj, in_window, n, t - 1 - t0, c->stream));
+    return HLB_OK;
+  }
+  hlb_status reverse(int64_t a, int64_t b, int64_t slot_a, int64_t cfree) {
+    while (b - a > 1 && cfree > 0) {
+      const int64_t l = b - a;
+      int64_t r = 1;
+      while (binom_sat(cfree + r, cfree) < l) ++r;
+      const int64_t right = std::min<int64_t>(binom_sat(cfree - 1 + r, cfree - 1), l - 1);
+      const int64_t m = b - right;
+      const int64_t slot_m = n_snap - cfree;
+      if (hlb_status st = restore(slot_a)) return st;
+      if (hlb_status st = advance(m - a)) return st;
+      if (hlb_status st = save(slot_m)) return st;
+      if (hlb_status st = reverse(m, b, slot_m, cfree - 1)) return st;
+      b = m;
+    }
+    for (int64_t t = b; t > a; --t) {  // no free slot left (or one step): recompute from a
+      if (hlb_status st = restore(slot_a)) return st;
+      if (hlb_status st = advance(t - 1 - a)) return st;
+      if (hlb_status st = adjoint_step(t)) return st;
+    }
+    return HLB_OK;
+  }
+};
+
+}  // namespace
+
+extern "C" hlb_status hlb_adjoint_run(hlb_ctx *c, int64_t n, int64_t obj_t0, int64_t obj_t1, int32_t n_snap,
+                                      double *J, double *dJ_dA, double *dJ_dphi, int64_t *forward_steps) {
+  if (hlb_status st = check_ctx(c)) return st;
+  if (n < 1 || n_snap < 1 || n_snap > 4096 || !J) return fail(HLB_EINVAL, "need n >= 1, 1 <= n_snap <= 4096, J");
+  if (c->cfg.storage != HLB_F64 || !c->adj.push)
+    return fail(HLB_ESTATE, "the adjoint needs FP64 storage and opt.adjoint = 1 at creation");
+  if (hlb_status st = bind(c)) return st;
+  const int64_t np = c->L.np, nio = (int64_t)c->iolets.size();
+  void *p = nullptr;
+  if (!c->adj.mu) {
+    if (hlb_status st = dev_alloc(c, &p, (size_t)Q * np * sizeof(double))) return st;
+    c->adj.mu = static_cast<double *>(p);
+    if (hlb_status st = dev_alloc(c, &p, (size_t)Q * np * sizeof(double))) return st;
+    c->adj.nu = static_cast<double *>(p);
+    if (hlb_status st = dev_alloc(c, &p, (size_t)np * sizeof(double))) return st;
+    c->adj.dphi = static_cast<double *>(p);
+    if (hlb_status st = dev_alloc(c, &p, sizeof(double))) return st;
+    c->adj.J = static_cast<double *>(p);
+  }
+  if (c->adj_dA_len < std::max<int64_t>(1, nio * n)) {
+    if (c->adj.dA) {
+      (void)hipFree(c->adj.dA);
+      c->dev_bytes -= c->adj_dA_len * (int64_t)sizeof(double);
+      c->adj.dA = nullptr;
+      c->adj_dA_len = 0;
+    }
+    if (hlb_status st = dev_alloc(c, &p, (size_t)std::max<int64_t>(1, nio * n) * sizeof(double))) return st;
+    c->adj.dA = static_cast<double *>(p);
+    c->adj_dA_len = std::max<int64_t>(1, nio * n);
+  }
+  // checkpoint slots, plus one for the caller's other population buffer
+  while ((int64_t)c->adj_slots.size() < (int64_t)n_snap + 1) {
+    if (hlb_status st = dev_alloc(c, &p, buf_bytes(c))) return st;
+    c->adj_slots.push_back(p);
+  }
+  // keep the caller's state: both buffers, time, flags, flux accumulator
+  const int cur0 = c->cur;
+  const bool direct0 = c->direct;
+  const int64_t t_start = c->t;
+  double acc0[4];
+  HIP_TRY(hipMemcpyAsync(acc0, c->d.acc, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipMemcpyAsync(c->adj_slots[n_snap], c->d.f[1 - cur0], buf_bytes(c), hipMemcpyDeviceToDevice, c->stream));
+  HIP_TRY(launch_zero(c->adj.mu, (int64_t)Q * np, c->stream));
+  HIP_TRY(launch_zero(c->adj.dphi, np, c->stream));
+  HIP_TRY(launch_zero(c->adj.J, 1, c->stream));
+  HIP_TRY(launch_zero(c->adj.dA, std::max<int64_t>(1, nio * n), c->stream));
+  Revolve R;
+  R.c = c;
+  R.t0 = t_start;
+  R.n = n;
+  R.w0 = obj_t0;
+  R.w1 = obj_t1;
+  R.n_snap = n_snap;
+  R.slot_t.assign(n_snap, 0);
+  hlb_status st = R.save(0);
+  if (!st) st = R.reverse(t_start, t_start + n, 0, n_snap - 1);
+  // put the caller's state back
+  if (!st) {
+    hipError_t e = hipMemcpyAsync(c->d.f[cur0], c->adj_slots[0], buf_bytes(c), hipMemcpyDeviceToDevice, c->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(c->d.f[1 - cur0], c->adj_slots[n_snap], buf_bytes(c), hipMemcpyDeviceToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(c->d.acc, acc0, 4 * sizeof(double), hipMemcpyHostToDevice, c->stream);
+    if (e != hipSuccess) st = fail(HLB_EDEVICE, "restoring the state: %s", hipGetErrorString(e));
+  }
+  c->cur = cur0;
+  c->direct = direct0;
+  c->t = t_start;
+  if (st) return st;
+  HIP_TRY(hipMemcpyAsync(J, c->adj.J, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  if (dJ_dA && nio > 0)
+    HIP_TRY(hipMemcpyAsync(dJ_dA, c->adj.dA, (size_t)nio * n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  std::vector<double> dphi_pos;
+  if (dJ_dphi) {
+    dphi_pos.resize(np);
+    HIP_TRY(hipMemcpyAsync(dphi_pos.data(), c->adj.dphi, np * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  }
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  if (dJ_dphi)
+    for (int64_t q = 0; q < np; ++q)
+      if (c->order_host[q] >= 0) dJ_dphi[c->order_host[q]] = dphi_pos[q];
+  if (forward_steps) *forward_steps = R.fwd;
+  if (!std::isfinite(*J)) return fail(HLB_ENUMERIC, "objective is not finite");
+  return HLB_OK;
+}

@@ -43,14 +43,15 @@ class hlb_iolet(ctypes.Structure):
 
 class hlb_options(ctypes.Structure):
     _fields_ = [("storage", ctypes.c_int32), ("order", ctypes.c_int32), ("xcd_remap", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("rho0", ctypes.c_double), ("max_device_bytes", ctypes.c_int64)]
+                ("adjoint", ctypes.c_int32), ("rho0", ctypes.c_double), ("max_device_bytes", ctypes.c_int64)]
 
 
 class hlb_info_t(ctypes.Structure):
     _fields_ = [("n_sites", ctypes.c_int64), ("n_padded", ctypes.c_int64), ("group_sites", ctypes.c_int64 * 6),
                 ("storage", ctypes.c_int32), ("order", ctypes.c_int32), ("bytes_per_lup", ctypes.c_double),
                 ("device_bytes", ctypes.c_int64), ("table_bytes_per_site", ctypes.c_double),
-                ("n_segments", ctypes.c_int64)]
+                ("n_segments", ctypes.c_int64), ("n_iolets", ctypes.c_int64), ("adjoint", ctypes.c_int32),
+                ("porous", ctypes.c_int32)]
 
 
 class hlb_stats_t(ctypes.Structure):
@@ -90,6 +91,7 @@ _SIGS = {
     "hlb_state_load": [_P, _P],
     "hlb_sync": [_P],
     "hlb_copy_bandwidth": [_i64, _i32, ctypes.POINTER(_d)],
+    "hlb_adjoint_run": [_P, _i64, _i64, _i64, _i32, _P, _P, _P, ctypes.POINTER(_i64)],
     "hlb_last_error": [],
 }
 EXPORTED = tuple(_SIGS)
@@ -223,7 +225,8 @@ def hlb_info(ctx) -> dict:
     _check(load().hlb_info(ctx, ctypes.byref(i)), "hlb_info")
     return dict(n_sites=i.n_sites, n_padded=i.n_padded, group_sites=list(i.group_sites)[:5], storage=i.storage,
                 order=i.order, bytes_per_lup=i.bytes_per_lup, device_bytes=i.device_bytes,
-                table_bytes_per_site=i.table_bytes_per_site, n_segments=i.n_segments)
+                table_bytes_per_site=i.table_bytes_per_site, n_segments=i.n_segments, n_iolets=i.n_iolets,
+                adjoint=i.adjoint, porous=i.porous)
 
 
 def hlb_macros(ctx, want=("rho", "u", "wss")):
@@ -310,6 +313,22 @@ def hlb_sync(ctx):
     _check(load().hlb_sync(ctx), "hlb_sync")
 
 
+def hlb_adjoint_run(ctx, n: int, obj_t0: int, obj_t1: int, n_snap: int, want_dA=True, want_dphi=True):
+    """Returns (J, dJ_dA [n_iolets][n] or None, dJ_dphi [n_sites] or None, forward_steps)."""
+    info = hlb_info(ctx)
+    nio = info["n_iolets"]
+    J = np.zeros(1)
+    dA = np.zeros((max(nio, 1), n)) if want_dA else None
+    dphi = np.zeros(info["n_sites"]) if want_dphi else None
+    fw = ctypes.c_int64()
+    P = lambda a: a.ctypes.data_as(_P) if a is not None else None
+    _check(load().hlb_adjoint_run(ctx, int(n), int(obj_t0), int(obj_t1), int(n_snap), P(J), P(dA), P(dphi),
+                                  ctypes.byref(fw)), "hlb_adjoint_run")
+    if dA is not None:
+        dA = dA[:nio]
+    return float(J[0]), dA, dphi, fw.value
+
+
 def hlb_copy_bandwidth(nbytes: int = 4 << 30, reps: int = 20) -> float:
     g = ctypes.c_double()
     _check(load().hlb_copy_bandwidth(int(nbytes), int(reps), ctypes.byref(g)), "hlb_copy_bandwidth")
@@ -325,18 +344,21 @@ class Simulation:
 
     ctx: ctypes.c_void_p
     n: int
+    iolet_kinds: list = None
 
     @classmethod
     def create(cls, geom, tau: float, storage: str = "f64", order: str = "lex", xcd_remap: int = 2,
-               rho0: float = 1.0, max_device_bytes: int = 0, tables=None):
+               rho0: float = 1.0, max_device_bytes: int = 0, tables=None, adjoint: bool = False):
         opt = hlb_default_options()
         opt.storage = STORAGE[storage]
         opt.order = ORDER[order]
         opt.xcd_remap = int(xcd_remap)
         opt.rho0 = float(rho0)
         opt.max_device_bytes = int(max_device_bytes)
+        opt.adjoint = 1 if adjoint else 0
         ctx = hlb_create(geom.coords, geom.types, geom.nbr, tau, geom.iolets, opt)
         sim = cls(ctx, int(geom.types.shape[0]))
+        sim.iolet_kinds = [int(io.kind) for io in geom.iolets]
         for k, io in enumerate(geom.iolets):
             tab = tables[k] if tables is not None and tables[k] is not None else getattr(io, "table", None)
             if tab is not None:

@@ -35,7 +35,7 @@ def test_exports_every_declared_symbol():
 
 def test_default_options():
     o = hlb.hlb_default_options()
-    assert (o.storage, o.order, o.xcd_remap, o.reserved, o.rho0, o.max_device_bytes) == (0, 1, 2, 0, 1.0, 0)
+    assert (o.storage, o.order, o.xcd_remap, o.adjoint, o.rho0, o.max_device_bytes) == (0, 1, 2, 0, 1.0, 0)
 
 
 @pytest.fixture(scope="module")
@@ -110,8 +110,12 @@ def test_rejects_bad_options(cyl):
     o.rho0 = -1.0
     _expect(hlb.HLB_EINVAL, hlb.hlb_create, cyl.coords, cyl.types, cyl.nbr, 0.8, cyl.iolets, o)
     o = hlb.hlb_default_options()
-    o.reserved = 1
+    o.adjoint = 2
     _expect(hlb.HLB_EINVAL, hlb.hlb_create, cyl.coords, cyl.types, cyl.nbr, 0.8, cyl.iolets, o)
+    o = hlb.hlb_default_options()
+    o.adjoint = 1
+    o.storage = hlb.HLB_F32_SHIFTED
+    _expect(hlb.HLB_EINVAL, hlb.hlb_create, cyl.coords, cyl.types, cyl.nbr, 0.8, cyl.iolets, o, match="FP64")
 
 
 def test_null_arguments():
