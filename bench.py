@@ -48,8 +48,11 @@ def tree_workload(target=20_000_000, seed=2, generations=8):
 
 
 def kernel_source_hash():
-    p = os.path.join(ROOT, "paper_2202_11770_amd", "csrc", "hlb_kernels.hip")
-    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+    """Hash of the sources the step kernel is compiled from."""
+    h = hashlib.sha256()
+    for name in ("hlb_device.h", "hlb_kernels.hip", "hlb_internal.h"):
+        h.update(open(os.path.join(ROOT, "paper_2202_11770_amd", "csrc", name), "rb").read())
+    return h.hexdigest()[:16]
 
 
 def stored_traffic(storage, n_sites):
