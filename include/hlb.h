@@ -116,7 +116,7 @@ typedef struct {
   int32_t order;       /* hlb_order (default HLB_ORDER_LEX) */
   int32_t xcd_remap;   /* K > 0: renumber the bulk kernel's workgroups so that
                           each of the 8 XCDs gets K consecutive tiles of every
-                          window of 8K tiles (default 2); 0: plain block order */
+                          window of 8K tiles (default 8); 0: plain block order */
   int32_t adjoint;     /* 1: also build the tables of hlb_adjoint_run (FP64
                           storage only; 72 more bytes per site); default 0 */
   double rho0;         /* reference density (default 1.0) */

@@ -288,7 +288,7 @@ hlb_status hlb_default_options(hlb_options *opt) {
   if (!opt) return fail(HLB_EINVAL, "null options");
   opt->storage = HLB_F64;
   opt->order = HLB_ORDER_LEX;
-  opt->xcd_remap = 2;
+  opt->xcd_remap = 8;
   opt->adjoint = 0;
   opt->rho0 = 1.0;
   opt->max_device_bytes = 0;

@@ -347,7 +347,7 @@ class Simulation:
     iolet_kinds: list = None
 
     @classmethod
-    def create(cls, geom, tau: float, storage: str = "f64", order: str = "lex", xcd_remap: int = 2,
+    def create(cls, geom, tau: float, storage: str = "f64", order: str = "lex", xcd_remap: int = 8,
                rho0: float = 1.0, max_device_bytes: int = 0, tables=None, adjoint: bool = False):
         opt = hlb_default_options()
         opt.storage = STORAGE[storage]

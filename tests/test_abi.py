@@ -35,7 +35,7 @@ def test_exports_every_declared_symbol():
 
 def test_default_options():
     o = hlb.hlb_default_options()
-    assert (o.storage, o.order, o.xcd_remap, o.adjoint, o.rho0, o.max_device_bytes) == (0, 1, 2, 0, 1.0, 0)
+    assert (o.storage, o.order, o.xcd_remap, o.adjoint, o.rho0, o.max_device_bytes) == (0, 1, 8, 0, 1.0, 0)
 
 
 @pytest.fixture(scope="module")

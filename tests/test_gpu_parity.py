@@ -34,7 +34,7 @@ def _oracle_run(g, tau, steps, tables=None, phi=None, init=None):
     return P, f
 
 
-def _gpu_run(g, tau, steps, storage="f64", order="lex", xcd=2, tables=None, phi=None, init=None):
+def _gpu_run(g, tau, steps, storage="f64", order="lex", xcd=8, tables=None, phi=None, init=None):
     sim = hlb.Simulation.create(g, tau, storage=storage, order=order, xcd_remap=xcd, tables=tables)
     if phi is not None:
         hlb.hlb_set_porosity(sim.ctx, phi)
