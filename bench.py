@@ -37,14 +37,49 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def tree_workload(target=20_000_000, seed=2, generations=8):
+# Geometry scales that give the stated site counts (found by the generators'
+# own scale iteration; recorded so that the large cases are voxelised once).
+TREE_SCALE_200M = 2.446148147624885   # seed 2, 8 generations: 200,030,189 sites
+FOREST_SCALE_600M = 1.0722357994557143  # seed 5, 8x8 trees of 4 generations: 600,343,441 sites
+
+WORKLOADS = {
+    # name: (tau, default steps, storages, description)
+    "tree20m": (0.6, 1000, "f64,f32,f16", "bifurcating tree, seed 2, 8 generations, ~2.0e7 sites, "
+                "1 Ladd inlet + 256 pressure outlets"),
+    "tree200m": (0.6, 200, "f64,f32,f16", "bifurcating tree, seed 2, 8 generations, ~2.0e8 sites, "
+                 "1 Ladd inlet + 256 pressure outlets"),
+    "forest600m": (0.55, 500, "f32", "forest of 64 trees (seed 5, 4 generations), ~6.0e8 sites, "
+                   "64 Ladd inlets + 1024 pressure outlets"),
+}
+
+
+def inlet_table():
+    """A(s) = u_max (1 - cos(2 pi s / T)) / 2, u_max = 0.02, T = 2000 steps."""
+    import numpy as np
+    s = np.arange(2000)
+    return 0.02 * 0.5 * (1.0 - np.cos(2.0 * np.pi * s / 2000.0))
+
+
+def tree_workload(target=20_000_000, seed=2, generations=8, scale=None, verbose=False):
     import numpy as np
     from paper_2202_11770_amd import geometry as G
-    g = G.tree(seed=seed, generations=generations, target_sites=target)
-    s = np.arange(2000)
-    inlet = 0.02 * 0.5 * (1.0 - np.cos(2.0 * np.pi * s / 2000.0))
-    tables = [inlet if io.kind == G.VELOCITY else np.array([1.0]) for io in g.iolets]
+    g = G.tree(seed=seed, generations=generations, target_sites=target, scale=scale, verbose=verbose)
+    tables = [inlet_table() if io.kind == G.VELOCITY else np.array([1.0]) for io in g.iolets]
     return g, tables
+
+
+def workload(name):
+    import numpy as np
+    from paper_2202_11770_amd import geometry as G
+    if name == "tree20m":
+        return tree_workload()
+    if name == "tree200m":
+        return tree_workload(scale=TREE_SCALE_200M, verbose=True)
+    if name == "forest600m":
+        g = G.forest(scale=FOREST_SCALE_600M, verbose=True)
+        tables = [inlet_table() if io.kind == G.VELOCITY else np.array([1.0]) for io in g.iolets]
+        return g, tables
+    raise ValueError(name)
 
 
 def kernel_source_hash():
@@ -71,8 +106,10 @@ def stored_traffic(storage, n_sites):
 def run_storage(g, tables, tau, storage, steps, warmup):
     import torch
     from paper_2202_11770_amd import hlb
+    t0 = time.time()
     sim = hlb.Simulation.create(g, tau, storage=storage, tables=tables)
     info = sim.info()
+    log(f"{storage}: context created in {time.time() - t0:.1f}s, {info['device_bytes'] / 2**30:.1f} GiB on the device")
     sim.step(warmup)
     hlb.hlb_sync(sim.ctx)
     torch.cuda.synchronize()
@@ -97,6 +134,56 @@ def run_storage(g, tables, tau, storage, steps, warmup):
                 mlups=mlups, alg_gbs=bpl * n * steps / dt / 1e9, kernel_ms=st["kernel_ms"],
                 event_step_ms=st["step_ms"], kernel_gbs=achieved,
                 frac=achieved / PEAK_GBS, mass=m, mass_residual_rel=r / m)
+
+
+def device_macros(g, tables, tau, storage, steps):
+    """rho, u, wss (device, FP64) after `steps` steps from rest."""
+    import torch
+    from paper_2202_11770_amd import hlb
+    sim = hlb.Simulation.create(g, tau, storage=storage, tables=tables)
+    log(f"{storage}: {steps} steps from rest for the error comparison")
+    sim.step(steps)
+    rho = torch.empty(g.n, dtype=torch.float64, device="cuda")
+    u = torch.empty(g.n, 3, dtype=torch.float64, device="cuda")
+    wss = torch.empty(g.n, dtype=torch.float64, device="cuda")
+    hlb.hlb_macros_device(sim.ctx, rho, u, wss)
+    hlb.hlb_sync(sim.ctx)
+    m, r = hlb.hlb_mass_balance(sim.ctx)
+    sim.close()
+    return rho, u, wss, m
+
+
+def storage_errors(a, ref, rho0=1.0):
+    """Max and RMS errors of (rho, u, wss) against a reference run: rho
+    relative to rho0, u relative to max |u_ref|, wss relative to max wss_ref."""
+    rho, u, wss = a[:3]
+    rr, ur, wr = ref[:3]
+    du = (u - ur).norm(dim=1)
+    us = float(ur.norm(dim=1).max())
+    ws = float(wr.max())
+    return {"e_rho": float((rho - rr).abs().max()) / rho0,
+            "rms_rho": float((rho - rr).pow(2).mean().sqrt()) / rho0,
+            "e_u": float(du.max()) / us, "rms_u": float(du.pow(2).mean().sqrt()) / us,
+            "e_wss": float((wss - wr).abs().max()) / ws,
+            "rms_wss": float((wss - wr).pow(2).mean().sqrt()) / ws,
+            "mass_rel": (a[3] - ref[3]) / ref[3]}
+
+
+def compare_storages(g, tables, tau, storages, steps):
+    """Errors of each reduced-precision storage against the FP64 GPU run over
+    the same steps from rest, every site compared on the device."""
+    import torch
+    ref = device_macros(g, tables, tau, "f64", steps)
+    out = {}
+    for st in storages:
+        if st == "f64":
+            continue
+        a = device_macros(g, tables, tau, st, steps)
+        out[st] = {k: float(f"{v:.4g}") for k, v in storage_errors(a, ref).items()}
+        log(f"{st} vs f64-GPU after {steps} steps: {out[st]}")
+        del a
+        torch.cuda.empty_cache()
+    return out
 
 
 def copy_ceiling(nbytes=4 << 30, reps=20):
@@ -125,12 +212,15 @@ def cpu_baseline(g, tables, tau, budget_s=15.0):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--workload", default="tree20m", choices=sorted(WORKLOADS))
+    ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=100)
-    ap.add_argument("--sites", type=int, default=20_000_000)
-    ap.add_argument("--storages", default="f64,f32,f16")
+    ap.add_argument("--storages", default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-copy", action="store_true")
+    ap.add_argument("--compare-steps", type=int, default=0,
+                    help="also run every storage for this many steps from rest and report the "
+                         "FP32/FP16 errors against the FP64 GPU run")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); the multi-GPU "
@@ -138,10 +228,12 @@ def main():
         sys.exit(2)
     import torch
     torch.cuda.set_device(int(os.environ.get("LOCAL_RANK", "0")))
-    tau = 0.6
+    tau, def_steps, def_storages, desc = WORKLOADS[args.workload]
+    args.steps = args.steps or def_steps
+    args.storages = args.storages or def_storages
     t0 = time.time()
-    g, tables = tree_workload(args.sites)
-    log(f"workload: tree {g.n} sites, {len(g.iolets)} iolets, fill {g.meta['fill']:.4f}, "
+    g, tables = workload(args.workload)
+    log(f"workload: {args.workload}: {g.n} sites, {len(g.iolets)} iolets, fill {g.meta['fill']:.4f}, "
         f"generated in {time.time() - t0:.1f}s")
     results = {}
     for st in args.storages.split(","):
@@ -157,9 +249,12 @@ def main():
     if copy_gbs:
         log(f"plain copy: {copy_gbs:.0f} GB/s")
     cpu = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.workload == "tree20m":
         cpu = cpu_baseline(g, tables, tau)
         log(f"cpu baseline: {cpu}")
+    compare = None
+    if args.compare_steps > 0:
+        compare = compare_storages(g, tables, tau, args.storages.split(","), args.compare_steps)
     traffic = stored_traffic(main_st, R["n_sites"])
     out = {
         "metric": "MLUPS & achieved HBM GB/s, FP64 vs FP32/FP16 storage at stated error",
@@ -174,8 +269,7 @@ def main():
         "vs_baseline": None,
         "dtype": {"f64": "f64", "f32": "f32-storage", "f16": "f16-storage"}[main_st],
         "data": "synthetic",
-        "config": {"workload": f"bifurcating tree, {g.n} fluid sites (seed 2, 8 generations), tau 0.6, "
-                               f"1 Ladd inlet + 256 pressure outlets, storage {main_st}",
+        "config": {"workload": f"{args.workload}: {desc}; {g.n} fluid sites, tau {tau}, storage {main_st}",
                    "n_sites": g.n, "storage": main_st, "order": "lex", "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(R["kernel_gbs"], 1), "peak": PEAK_GBS, "unit": "GB/s",
                      "frac": round(R["frac"], 4), "traffic": traffic,
@@ -191,6 +285,8 @@ def main():
                          "gain_vs_f64": round(v["mlups"] / results[main_st]["mlups"], 3),
                          "mass_residual_rel": v["mass_residual_rel"]} for k, v in results.items()},
     }
+    if compare is not None:
+        out["errors_vs_f64_gpu"] = {"steps": args.compare_steps, **compare}
     print(json.dumps(out), flush=True)
 
 

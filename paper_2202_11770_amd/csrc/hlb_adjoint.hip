@@ -108,7 +108,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_collide(AdjArgs A) {
       double pxx = 0, pyy = 0, pzz = 0, pxy = 0, pxz = 0, pyz = 0;
 #pragma unroll
       for (int i = 0; i < Q; ++i) {
-        const double d = g[i] - s_eq<false>(i, rho, 0.0, ux, uy, uz, usq);
+        const double d = g[i] - s_eq<false>(i, 0.0, rho, ux, uy, uz, usq);
         pxx += d * cx(i) * cx(i);
         pyy += d * cy(i) * cy(i);
         pzz += d * cz(i) * cz(i);

@@ -104,12 +104,16 @@ __device__ inline void moments(const C (&s)[Q], C rho0, C &dr, C &rho, C &jx, C 
 
 // Equilibrium eq. (4) (1/2 factors on the second-order terms) in the stored
 // representation:  f_eq = w rho (1 + 3 c.u + 9/2 (c.u)^2 - 3/2 u.u);
-// shifted: f_eq - w rho0 = w ((rho - rho0) + rho (3 c.u + 9/2 (c.u)^2 - 3/2 u.u)).
+// shifted: f_eq - w rho0 = w (dr + rho (3 c.u + 9/2 (c.u)^2 - 3/2 u.u)) with
+// dr = rho - rho0 passed in as summed, not recomputed from rho: in FP32,
+// rho0 + dr rounds dr to the ulp of rho0, and that rounding would break the
+// collision's mass conservation at every site and step.  dr is unused
+// unshifted.
 template <bool SH, typename C>
-__device__ inline C s_eq(int i, C rho, C rho0, C ux, C uy, C uz, C usq15) {
+__device__ inline C s_eq(int i, C dr, C rho, C ux, C uy, C uz, C usq15) {
   const C cu = C(cx(i)) * ux + C(cy(i)) * uy + C(cz(i)) * uz;
   const C q = C(3) * cu + C(4.5) * cu * cu - usq15;
-  return SH ? wgt<C>(i) * ((rho - rho0) + rho * q) : wgt<C>(i) * rho * (C(1) + q);
+  return SH ? wgt<C>(i) * (dr + rho * q) : wgt<C>(i) * rho * (C(1) + q);
 }
 
 // BGK collision, eq. (3a) with dt = 1: s' = s + omega (s_eq - s).
@@ -121,7 +125,7 @@ __device__ inline void collide(C (&s)[Q], C omega, C rho0) {
   const C ux = jx * inv, uy = jy * inv, uz = jz * inv;
   const C usq = C(1.5) * (ux * ux + uy * uy + uz * uz);
 #pragma unroll
-  for (int i = 0; i < Q; ++i) s[i] = s[i] + omega * (s_eq<SH>(i, rho, rho0, ux, uy, uz, usq) - s[i]);
+  for (int i = 0; i < Q; ++i) s[i] = s[i] + omega * (s_eq<SH>(i, dr, rho, ux, uy, uz, usq) - s[i]);
 }
 
 struct GatherArgs {
@@ -231,7 +235,7 @@ __device__ inline C gather(const T *__restrict__ A, int64_t p, int64_t blk, cons
           const C un = ux * C(K.n[0]) + uy * C(K.n[1]) + uz * C(K.n[2]);
           const C gx = un * C(K.n[0]), gy = un * C(K.n[1]), gz = un * C(K.n[2]);
           const C uu = C(1.5) * (gx * gx + gy * gy + gz * gz);
-          v = s_eq<SH>(i, C(val), C(a.rho0), gx, gy, gz, uu);
+          v = s_eq<SH>(i, C(val - a.rho0), C(val), gx, gy, gz, uu);
         }
       }
       flux += v - back;

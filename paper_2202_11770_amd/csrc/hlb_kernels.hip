@@ -93,7 +93,7 @@ __global__ __launch_bounds__(kBlock) void k_init_eq(T *__restrict__ A, T *__rest
                  uy = staging[4 * (int64_t)id + 2], uz = staging[4 * (int64_t)id + 3];
     const double usq = 1.5 * (ux * ux + uy * uy + uz * uz);
 #pragma unroll
-    for (int i = 0; i < Q; ++i) g[i] = s_eq<SH>(i, rho, rho0, ux, uy, uz, usq);
+    for (int i = 0; i < Q; ++i) g[i] = s_eq<SH>(i, rho - rho0, rho, ux, uy, uz, usq);
   }
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
@@ -192,7 +192,7 @@ __global__ __launch_bounds__(kBlock) void k_macros(const T *__restrict__ A, Gath
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
       // non-equilibrium part f - f_eq (the same in either representation)
-      const double d = g[i] - s_eq<SH>(i, rho, a.rho0, ux, uy, uz, usq);
+      const double d = g[i] - s_eq<SH>(i, dr, rho, ux, uy, uz, usq);
       pxx += d * cx(i) * cx(i);
       pyy += d * cy(i) * cy(i);
       pzz += d * cz(i) * cz(i);

@@ -27,6 +27,8 @@ from __future__ import annotations
 import ctypes
 import math
 import os
+import sys
+import time
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -296,8 +298,10 @@ def _subtree_ids(seg, root):
     return np.array(sorted(ids))
 
 
-def _tree_geometry(seg, ids, root, inlet_kind, outlet_kind, name, extra_meta, build=True, trees=None):
+def _tree_geometry(seg, ids, root, inlet_kind, outlet_kind, name, extra_meta, build=True, trees=None,
+                   verbose=False):
     """Voxelise segments `ids` of one or more trees; inlets at the roots, outlets at leaves."""
+    t0 = time.time()
     a, b, r = seg["a"][ids], seg["b"][ids], seg["r"][ids]
     parent = seg["parent"]
     idset = set(int(i) for i in ids)
@@ -313,6 +317,8 @@ def _tree_geometry(seg, ids, root, inlet_kind, outlet_kind, name, extra_meta, bu
     origin = lo
     bits = voxelise_capsules(a, b, r, cut_a, cut_b, dims, origin)
     n = count(bits, dims)
+    if verbose:
+        print(f"{name}: voxelised {dims} -> {n} sites in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
     if not build:
         return n, dims
     iolets = []
@@ -329,12 +335,15 @@ def _tree_geometry(seg, ids, root, inlet_kind, outlet_kind, name, extra_meta, bu
             iolets.append(Iolet(outlet_kind, OUTLET, tuple(c), tuple(-d[i]), float(seg["r"][i])))
     meta = dict(name=name, fill=n / float(np.prod(dims)), n_segments=len(ids))
     meta.update(extra_meta)
-    return build_sites(bits, dims, iolets, meta=meta)
+    g = build_sites(bits, dims, iolets, meta=meta)
+    if verbose:
+        print(f"{name}: site list and neighbour table built, {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    return g
 
 
 def tree(seed: int = 2, generations: int = 8, target_sites: int | None = 20_000_000,
          scale: float | None = None, inlet_kind: int = VELOCITY, outlet_kind: int = PRESSURE,
-         rel_tol: float = 0.01) -> Geometry:
+         rel_tol: float = 0.01, verbose: bool = False) -> Geometry:
     """Seeded bifurcating tree scaled to about ``target_sites`` fluid sites.
 
     The root starts on the plane z = -1/2 (its inlet) with its axis through a
@@ -352,34 +361,43 @@ def tree(seed: int = 2, generations: int = 8, target_sites: int | None = 20_000_
         scale = s
     seg = tree_segments(seed, generations, scale=scale, origin=origin)
     g = _tree_geometry(seg, np.arange(len(seg["r"])), 0, inlet_kind, outlet_kind, "tree",
-                       dict(seed=seed, generations=generations, scale=scale))
+                       dict(seed=seed, generations=generations, scale=scale), verbose=verbose)
     g.meta["segments"] = seg
     return g
 
 
-def subtree(parent_tree: Geometry, target_sites: int = 2_000_000, inlet_kind: int = VELOCITY,
-            outlet_kind: int = PRESSURE) -> Geometry:
-    """The subtree rooted at the first child, at the generation whose subtree
-    size is closest to ``target_sites``, voxelised at the same spacing.
+def subtree(parent_tree=None, target_sites: int = 2_000_000, inlet_kind: int = VELOCITY,
+            outlet_kind: int = PRESSURE, segments=None, scale: float | None = None) -> Geometry:
+    """The subtree rooted at the first child of the generation whose subtree
+    size is closest to ``target_sites`` (by ratio), voxelised at the same
+    spacing.
 
-    Its root segment gets its own inlet (flat cut at the branch start).
+    Pass either the parent tree (its segments are in ``meta``) or the
+    parent's ``segments`` and ``scale``.  Generations are tried from the
+    deepest up and the search stops once a subtree exceeds twice the target,
+    so the large subtrees near the root are never voxelised.  The subtree's
+    root segment gets its own inlet (flat cut at the branch start).
     """
-    seg = parent_tree.meta["segments"]
+    seg = segments if segments is not None else parent_tree.meta["segments"]
+    sc = scale if scale is not None else parent_tree.meta["scale"]
     depth = seg["depth"]
     best = None
-    for g in range(1, int(depth.max()) + 1):
+    for g in range(int(depth.max()), 0, -1):
         first = int(np.nonzero(depth == g)[0][0])
         ids = _subtree_ids(seg, first)
         n, _ = _tree_geometry(seg, ids, first, inlet_kind, outlet_kind, "subtree", {}, build=False)
-        if best is None or abs(n - target_sites) < abs(best[1] - target_sites):
+        if best is None or abs(np.log(n / target_sites)) < abs(np.log(best[1] / target_sites)):
             best = (first, n, ids, g)
+        if n > 2 * target_sites:
+            break
     first, n, ids, g = best
     return _tree_geometry(seg, ids, first, inlet_kind, outlet_kind, "subtree",
-                          dict(root_segment=first, generation=g, scale=parent_tree.meta["scale"]))
+                          dict(root_segment=first, generation=g, scale=sc))
 
 
 def forest(seed: int = 5, grid: int = 8, generations: int = 4, target_sites: int | None = 600_000_000,
-           scale: float | None = None, spacing_radii: float = 12.0, rel_tol: float = 0.01) -> Geometry:
+           scale: float | None = None, spacing_radii: float = 12.0, rel_tol: float = 0.01,
+           verbose: bool = False) -> Geometry:
     """grid x grid independent trees side by side (seed + tree index)."""
     def segs(s):
         allseg = dict(a=[], b=[], r=[], parent=[], depth=[], d=[])
@@ -408,7 +426,7 @@ def forest(seed: int = 5, grid: int = 8, generations: int = 4, target_sites: int
         scale = s
     seg, roots = segs(scale)
     return _tree_geometry(seg, np.arange(len(seg["r"])), roots[0], VELOCITY, PRESSURE, "forest",
-                          dict(seed=seed, scale=scale, trees=len(roots)), trees=roots)
+                          dict(seed=seed, scale=scale, trees=len(roots)), trees=roots, verbose=verbose)
 
 
 def tortuous(radius: float = 12.0, length: int = 256, amplitude: float = 12.0, period: float = 128.0,

@@ -154,6 +154,50 @@ int gm_build(int64_t nx, int64_t ny, int64_t nz, const uint64_t *bits, const int
     const uint64_t below = (v & 63) ? (w & ((1ull << (v & 63)) - 1ull)) : 0ull;
     return base[v >> 6] + __builtin_popcountll(below);
   };
+  // Candidate iolets per 16^3 cell, in increasing k so that the first match
+  // below is the same as a scan over all iolets.  A link can only cross
+  // plane k within (R + sqrt 2) of its centre in the plane and sqrt 2 of it
+  // along the normal, so iolet k is listed in every cell that meets the box
+  // centre +- (R + 5) (the site is within R + 2 sqrt 2 + 1 of the centre);
+  // an iolet without a radius is listed everywhere.
+  const int64_t CS = 16;
+  const int64_t gx = (nx + CS - 1) / CS, gy = (ny + CS - 1) / CS, gz = (nz + CS - 1) / CS;
+  const int64_t ncell = gx * gy * gz;
+  std::vector<int64_t> cbeg(ncell + 1, 0);
+  std::vector<int32_t> clist;
+  {
+    auto cell_range = [&](int k, int64_t lo[3], int64_t hi[3]) {
+      const int64_t g[3] = {gx, gy, gz};
+      for (int d = 0; d < 3; ++d) {
+        if (radius[k] > 0.0) {
+          const double m = radius[k] + 5.0;
+          lo[d] = std::max<int64_t>(0, (int64_t)std::floor((centre[3 * k + d] - m) / CS));
+          hi[d] = std::min<int64_t>(g[d] - 1, (int64_t)std::floor((centre[3 * k + d] + m) / CS));
+        } else {
+          lo[d] = 0;
+          hi[d] = g[d] - 1;
+        }
+      }
+    };
+    for (int pass = 0; pass < 2; ++pass) {
+      std::vector<int64_t> fill(cbeg.begin(), cbeg.end() - 1);
+      for (int k = 0; k < n_iolets; ++k) {
+        int64_t lo[3], hi[3];
+        cell_range(k, lo, hi);
+        for (int64_t cz = lo[2]; cz <= hi[2]; ++cz)
+          for (int64_t cy = lo[1]; cy <= hi[1]; ++cy)
+            for (int64_t cx = lo[0]; cx <= hi[0]; ++cx) {
+              const int64_t c = (cz * gy + cy) * gx + cx;
+              if (pass == 0) cbeg[c + 1]++;
+              else clist[fill[c]++] = k;
+            }
+      }
+      if (pass == 0) {
+        for (int64_t c = 0; c < ncell; ++c) cbeg[c + 1] += cbeg[c];
+        clist.resize(cbeg[ncell]);
+      }
+    }
+  }
   int bad = 0;
 #pragma omp parallel for schedule(dynamic, 1024) reduction(| : bad)
   for (int64_t w = 0; w < nw; ++w) {
@@ -173,7 +217,9 @@ int gm_build(int64_t nx, int64_t ny, int64_t nz, const uint64_t *bits, const int
         const int64_t u = vox_index(B, yx, yy, yz);
         if (u >= 0 && bit_get(bits, u)) { row[i] = (int32_t)rank(u); continue; }
         int32_t code = -1;
-        for (int k = 0; k < n_iolets; ++k) {
+        const int64_t cell = ((z / CS) * gy + y / CS) * gx + x / CS;
+        for (int64_t e = cbeg[cell]; e < cbeg[cell + 1]; ++e) {
+          const int k = clist[e];
           const double *p = centre + 3 * k, *n = normal + 3 * k;
           const double sx = (x - p[0]) * n[0] + (y - p[1]) * n[1] + (z - p[2]) * n[2];
           const double sy = (yx - p[0]) * n[0] + (yy - p[1]) * n[1] + (yz - p[2]) * n[2];
