@@ -127,7 +127,7 @@ typedef struct {
 hlb_status hlb_default_options(hlb_options *opt);
 
 /* Create a simulation (Sec. 3.2.1: device set-up).
- *   n_sites   number of fluid sites, 1 <= n_sites < 2^30 - 2^12
+ *   n_sites   number of fluid sites, 1 <= n_sites < 2^30 - 2^13
  *   coords    [n][3] int32 lattice coordinates, each in [0, 2^20)
  *   site_type [n] uint8, HLB_SITE_*; must agree with the link codes
  *   nbr       [n][19] int32 push-direction table: nbr[x][i] = id of the site
@@ -202,7 +202,8 @@ hlb_status hlb_time(const hlb_ctx *ctx, int64_t *t);
 
 typedef struct {
   int64_t n_sites;          /* fluid sites */
-  int64_t n_padded;         /* sites incl. padding that keeps each group wave-aligned */
+  int64_t n_padded;         /* positions incl. padding: each group starts on a multiple of
+                               256, the total is a multiple of 4096 (one storage tile) */
   int64_t group_sites[6];   /* sites per group: bulk+wall, inlet, outlet,
                                inlet+wall, outlet+wall, (unused) */
   int32_t storage;          /* hlb_storage */

@@ -21,9 +21,9 @@ using namespace dev;
 
 struct AdjArgs {
   GatherArgs a;             // forward gather arguments, tables at t-1
-  const double *S;          // s_{t-1}: post-collision state at t-1, [19][np]
-  double *mu;               // mu_t in, mu_{t-1} out, [19][np]
-  double *nu;               // nu_t, [19][np]
+  const double *S;          // s_{t-1}: post-collision state at t-1 (tiled, as the state)
+  double *mu;               // mu_t in, mu_{t-1} out (tiled)
+  double *nu;               // nu_t (tiled)
   const int32_t *push;      // [18][np]: position of x + c_i, or the link code
   const int32_t *order;     // caller id per position (-1: padding)
   double omega, tau;
@@ -72,7 +72,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_collide(AdjArgs A) {
     const double ux = jx / rho, uy = jy / rho, uz = jz / rho;
     double m[Q], nu[Q];
 #pragma unroll
-    for (int i = 0; i < Q; ++i) m[i] = A.mu[(int64_t)i * a.np + p];
+    for (int i = 0; i < Q; ++i) m[i] = A.mu[pidx((int32_t)p, i)];
     double ea, ebx, eby, ebz;
     eq_transpose(m, rho, ux, uy, uz, ea, ebx, eby, ebz);
 #pragma unroll
@@ -144,7 +144,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_collide(AdjArgs A) {
     for (int i = 1; i < Q; ++i) {
       const int32_t c = code[i - 1];
       if (c == HLB_LINK_WALL) {
-        const double back = A.S[(int64_t)opp(i) * a.np + p];
+        const double back = A.S[pidx((int32_t)p, opp(i))];
         dphi += nu[i] * (wgt<double>(i) * a.rho0 - back);
       } else if (c < HLB_LINK_WALL) {
         const int k = -c - 2;
@@ -155,7 +155,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_collide(AdjArgs A) {
     }
     A.dphi[p] += dphi;
 #pragma unroll
-    for (int i = 0; i < Q; ++i) A.nu[(int64_t)i * a.np + p] = nu[i];
+    for (int i = 0; i < Q; ++i) A.nu[pidx((int32_t)p, i)] = nu[i];
   }
   const double s = wave_sum(jsum);
   if ((threadIdx.x & 63) == 0 && s != 0.0) atomicAdd(A.J, s);
@@ -169,17 +169,17 @@ __global__ __launch_bounds__(kBlock) void k_adj_stream(AdjArgs A) {
   const double ph = POROUS ? a.phi[p] : 0.0;
   double m[Q];
   bool pressure = false;
-  m[0] = A.nu[p];
+  m[0] = A.nu[pidx((int32_t)p, 0)];
 #pragma unroll
   for (int i = 1; i < Q; ++i) {
     // s_{t-1}[i][p] was read by the site at p + c_i, or reflected back to p
     const int32_t c = A.push[(int64_t)(i - 1) * a.np + p];
     if (c >= 0) {
-      m[i] = A.nu[(int64_t)i * a.np + c];
+      m[i] = A.nu[pidx((int32_t)c, i)];
     } else if (c == HLB_LINK_WALL) {
-      m[i] = (1.0 - ph) * A.nu[(int64_t)opp(i) * a.np + p];
+      m[i] = (1.0 - ph) * A.nu[pidx((int32_t)p, opp(i))];
     } else if (a.io[-c - 2].kind == HLB_IOLET_VELOCITY) {
-      m[i] = A.nu[(int64_t)opp(i) * a.np + p];
+      m[i] = A.nu[pidx((int32_t)p, opp(i))];
     } else {
       m[i] = 0.0;  // replaced by the ghost-density equilibrium
       pressure = true;
@@ -189,7 +189,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_stream(AdjArgs A) {
     // the ghost equilibrium depends on the site's u at t-1 (moments of s_{t-1})
     double s[Q];
 #pragma unroll
-    for (int i = 0; i < Q; ++i) s[i] = A.S[(int64_t)i * a.np + p];
+    for (int i = 0; i < Q; ++i) s[i] = A.S[pidx((int32_t)p, i)];
     double dr, rho, jx, jy, jz;
     moments<false>(s, 0.0, dr, rho, jx, jy, jz);
     const double ux = jx / rho, uy = jy / rho, uz = jz / rho;
@@ -207,14 +207,14 @@ __global__ __launch_bounds__(kBlock) void k_adj_stream(AdjArgs A) {
       const double dx = wgt<double>(o) * rk * (3.0 * cx(o) + 9.0 * cu * cx(o) - 3.0 * gx);
       const double dy = wgt<double>(o) * rk * (3.0 * cy(o) + 9.0 * cu * cy(o) - 3.0 * gy);
       const double dz = wgt<double>(o) * rk * (3.0 * cz(o) + 9.0 * cu * cz(o) - 3.0 * gz);
-      const double coef = A.nu[(int64_t)o * a.np + p] * (dx * K.n[0] + dy * K.n[1] + dz * K.n[2]) / rho;
+      const double coef = A.nu[pidx((int32_t)p, o)] * (dx * K.n[0] + dy * K.n[1] + dz * K.n[2]) / rho;
 #pragma unroll
       for (int j = 0; j < Q; ++j)
         m[j] += coef * (K.n[0] * (cx(j) - ux) + K.n[1] * (cy(j) - uy) + K.n[2] * (cz(j) - uz));
     }
   }
 #pragma unroll
-  for (int i = 0; i < Q; ++i) A.mu[(int64_t)i * a.np + p] = m[i];
+  for (int i = 0; i < Q; ++i) A.mu[pidx((int32_t)p, i)] = m[i];
 }
 
 inline unsigned blocks_of(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }

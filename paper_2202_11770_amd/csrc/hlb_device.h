@@ -52,6 +52,30 @@ __device__ inline C rest(int i, C rho0) {
   return SH ? C(0) : wgt<C>(i) * rho0;
 }
 
+// Element index of direction i of position q in a tiled population buffer
+// ([np/kPopTile][19][kPopTile]).  Positions are below 2^30, so the tile
+// arithmetic stays in 32 bits.
+__device__ inline int64_t pidx(int32_t q, int i) {
+  const int32_t row = (q >> kPopTileShift) * Q + i;
+  return ((int64_t)row << kPopTileShift) + (int64_t)(q & (int32_t)(kPopTile - 1));
+}
+
+// Address of direction i of position q.  NARROW: the whole buffer is at most
+// 4 GiB, so the byte offset is formed in 32 bits and the access takes the
+// buffer's scalar base plus a 32-bit vector offset, which saves the 64-bit
+// address arithmetic and the registers of 18 in-flight 64-bit addresses.
+template <bool NARROW, typename T>
+__device__ inline T *at(T *A, int32_t q, int i) {
+  if constexpr (NARROW) {
+    const uint32_t row = (uint32_t)((q >> kPopTileShift) * Q + i);
+    const uint32_t e = (row << kPopTileShift) + (uint32_t)(q & (int32_t)(kPopTile - 1));
+    using B = typename std::conditional<std::is_const<T>::value, const char, char>::type;
+    return reinterpret_cast<T *>(reinterpret_cast<B *>(A) + e * (uint32_t)sizeof(T));
+  } else {
+    return A + pidx(q, i);
+  }
+}
+
 __device__ inline double ld(const double *p) { return *p; }
 __device__ inline float ld(const float *p) { return *p; }
 __device__ inline float ld(const _Float16 *p) { return static_cast<float>(*p); }
@@ -149,8 +173,8 @@ static_assert(kSegRow == 20, "segment rows are five 16-byte vectors");
 
 // Source offsets of the 18 incoming links of bulk+wall position p, whose
 // kSegBlock-position block is blk: off[i-1] = source - p, the source being
-// a fluid position in [0, np) or, for a wall link, the site's own slot of
-// direction opp(i) (offset +-np, outside [0, np)).
+// a fluid position in [0, np), or for a wall link an offset of +-np that
+// leaves [0, np) (the link then reads the site's own direction opp(i)).
 __device__ inline void bulk_offsets(const GatherArgs &a, int64_t p, int64_t blk, int32_t (&off)[Q - 1]) {
   const int32_t s = a.seg_base[blk] + (int32_t)ld_stream(a.seg_delta + p);
   const int4 *row = reinterpret_cast<const int4 *>(a.seg_off + (int64_t)s * kSegRow);
@@ -180,23 +204,27 @@ __device__ inline void bulk_offsets(const GatherArgs &a, int64_t p, int64_t blk,
 // Returns the mass the boundary rules added (filled - reflected).
 // IOLET = false: the site has only fluid and wall links.
 // blk: the kSegBlock-position block of p (bulk+wall group only).
-template <bool IOLET, bool POROUS, bool SH, typename T, typename C>
+// NARROW: see at().
+template <bool IOLET, bool POROUS, bool SH, bool NARROW = false, typename T, typename C>
 __device__ inline C gather(const T *__restrict__ A, int64_t p, int64_t blk, const GatherArgs &a, C (&g)[Q]) {
   const int64_t np = a.np;
   C flux = 0;
   if constexpr (!IOLET) {
-    // Bulk+wall group: every link, bounce-back included, is a plain load at
-    // p + off from direction array i; the offsets are fetched before the
-    // 18 gathers are issued.
+    // Bulk+wall group: every link, bounce-back included, is one load; the
+    // offsets are fetched before the 18 gathers are issued.
     int32_t off[Q - 1];
     bulk_offsets(a, p, blk, off);
-    g[0] = ld(A + p);
+    const int32_t p32 = (int32_t)p;
+    g[0] = ld(at<NARROW>(A, p32, 0));
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
-      const int64_t j = p + (int64_t)off[i - 1];
-      C v = ld(A + (int64_t)i * np + j);
+      // a wall link's offset leaves [0, np): it reads the site's own
+      // direction opp(i)
+      const int32_t j = p32 + off[i - 1];
+      const bool wall = (uint32_t)j >= (uint32_t)np;
+      C v = ld(at<NARROW>(A, wall ? p32 : j, wall ? opp(i) : i));
       if constexpr (POROUS) {
-        if ((uint64_t)j >= (uint64_t)np) {
+        if (wall) {
           const C nv = v - C(a.phi[p]) * (v - rest<SH, C>(i, C(a.rho0)));
           flux += nv - v;
           v = nv;
@@ -205,23 +233,34 @@ __device__ inline C gather(const T *__restrict__ A, int64_t p, int64_t blk, cons
       g[i] = v;
     }
   } else {
-    C own[Q];
-#pragma unroll
-    for (int i = 0; i < Q; ++i) own[i] = ld(A + (int64_t)i * np + p);
     // velocity at time t: moments of the site's own post-collision state
     // (the collision conserves rho and rho u)
-    C dr, rho, jx, jy, jz;
-    moments<SH>(own, C(a.rho0), dr, rho, jx, jy, jz);
-    const C ux = jx / rho, uy = jy / rho, uz = jz / rho;
-    g[0] = own[0];
+    C ux, uy, uz;
+    {
+      C own[Q];
+#pragma unroll
+      for (int i = 0; i < Q; ++i) own[i] = ld(at<NARROW>(A, (int32_t)p, i));
+      C dr, rho, jx, jy, jz;
+      moments<SH>(own, C(a.rho0), dr, rho, jx, jy, jz);
+      ux = jx / rho;
+      uy = jy / rho;
+      uz = jz / rho;
+    }
+    // The reflected values are read again below (cache hits) instead of
+    // being kept live with the 19 gathered ones: the empty asm hides that
+    // q == p, so the compiler cannot merge those reads with the ones above
+    // and keep 19 more registers for them.
+    int32_t q = (int32_t)p;
+    asm volatile("" : "+v"(q));
+    g[0] = ld(at<NARROW>(A, q, 0));
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
       const int32_t code = a.nbr_io[(int64_t)(i - 1) * a.nio + (p - a.io_begin)];
       if (code >= 0) {
-        g[i] = ld(A + (int64_t)i * np + code);
+        g[i] = ld(at<NARROW>(A, code, i));
         continue;
       }
-      const C back = own[opp(i)];
+      const C back = ld(at<NARROW>(A, q, opp(i)));
       C v;
       if (code == HLB_LINK_WALL) {
         v = back;

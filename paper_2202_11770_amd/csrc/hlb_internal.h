@@ -25,6 +25,14 @@ constexpr int64_t kGroupAlign = 256;
 // relative to the first segment of its kSegBlock-position block.
 constexpr int kSegRow = 20;
 constexpr int64_t kSegBlock = 256;
+// Population buffers are tiled: positions are cut into tiles of kPopTile
+// consecutive positions and a tile stores its 19 direction runs one after
+// the other, [np / kPopTile][19][kPopTile].  Every wavefront still reads and
+// writes 64 consecutive elements per direction, but the 38 streams of a step
+// land in one region of memory instead of 38 regions np elements apart,
+// which HBM serves at a higher rate.  np is a multiple of kPopTile.
+constexpr int kPopTileShift = 12;
+constexpr int64_t kPopTile = int64_t(1) << kPopTileShift;
 
 struct IoletDev {
   int32_t kind;     // HLB_IOLET_VELOCITY / HLB_IOLET_PRESSURE
@@ -36,7 +44,7 @@ struct IoletDev {
 
 struct Layout {
   int64_t n_sites = 0;
-  int64_t np = 0;               // padded site count = stride of one direction array
+  int64_t np = 0;               // padded site count (multiple of kPopTile)
   int64_t gbeg[kGroups + 1] = {0};
   int64_t gcnt[kGroups] = {0};
   int64_t io_begin = 0;         // first position of the iolet groups
@@ -45,7 +53,7 @@ struct Layout {
 };
 
 struct DevPtrs {
-  void *f[2] = {nullptr, nullptr};  // population buffers, [19][np] of the storage type
+  void *f[2] = {nullptr, nullptr};  // population buffers, [np/kPopTile][19][kPopTile] of the storage type
   int32_t *seg_off = nullptr;       // [nseg][kSegRow] bulk+wall source offsets per segment
   int32_t *seg_base = nullptr;      // [ceil(n0 / kSegBlock)] first segment of each block
   uint8_t *seg_delta = nullptr;     // [n0] segment of each position minus its block's first

@@ -34,8 +34,19 @@ using namespace dev;
 // the iolet groups, so that their longer-latency work starts first and
 // overlaps the bulk blocks; the remaining blocks take the bulk+wall group.
 // Every block, hence every wavefront, runs one group's code path only.
-template <typename T, bool POROUS>
-__global__ __launch_bounds__(kBlock) void k_step(const T *__restrict__ A, T *__restrict__ B, GatherArgs a,
+// Per storage type, measured on the 2e7-site tree: the minimum waves per
+// SIMD the step kernel is compiled for (the rare iolet blocks spill to fit,
+// the bulk path does not), and whether population addresses use 32-bit byte
+// offsets when a buffer allows it (see at()).  FP64: the natural 4 waves and
+// 32-bit offsets; FP32: the natural 5 waves and 64-bit addresses (32-bit
+// offsets measured 3% slower); FP16: 8 waves and 32-bit offsets.
+template <typename T>
+constexpr int kStepWaves = std::is_same<T, double>::value ? 4 : (std::is_same<T, float>::value ? 5 : 8);
+template <typename T>
+constexpr bool kStepNarrow = !std::is_same<T, float>::value;
+
+template <typename T, bool POROUS, bool NARROW>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kStepWaves<T>, 8))) void k_step(const T *__restrict__ A, T *__restrict__ B, GatherArgs a,
                                                  const int32_t *__restrict__ order, int64_t n0, int64_t nb_io,
                                                  int64_t nb_bulk, int xcd_chunk, typename Acc<T>::type omega,
                                                  double *acc) {
@@ -47,10 +58,10 @@ __global__ __launch_bounds__(kBlock) void k_step(const T *__restrict__ A, T *__r
     const int64_t p = a.io_begin + b * kBlock + threadIdx.x;
     if (p < a.np && order[p] >= 0) {
       C g[Q];
-      flux = gather<true, POROUS, SH>(A, p, 0, a, g);
+      flux = gather<true, POROUS, SH, NARROW>(A, p, 0, a, g);
       collide<SH>(g, omega, C(a.rho0));
 #pragma unroll
-      for (int i = 0; i < Q; ++i) st(B + (int64_t)i * a.np + p, g[i]);
+      for (int i = 0; i < Q; ++i) st(at<NARROW>(B, (int32_t)p, i), g[i]);
     }
     const double s = wave_sum(double(flux));
     if ((threadIdx.x & 63) == 0 && s != 0.0) atomicAdd(acc, s);
@@ -59,10 +70,10 @@ __global__ __launch_bounds__(kBlock) void k_step(const T *__restrict__ A, T *__r
     const int64_t p = blk * kBlock + threadIdx.x;
     if (p < n0) {
       C g[Q];
-      flux = gather<false, POROUS, SH>(A, p, blk, a, g);
+      flux = gather<false, POROUS, SH, NARROW>(A, p, blk, a, g);
       collide<SH>(g, omega, C(a.rho0));
 #pragma unroll
-      for (int i = 0; i < Q; ++i) st(B + (int64_t)i * a.np + p, g[i]);
+      for (int i = 0; i < Q; ++i) st(at<NARROW>(B, (int32_t)p, i), g[i]);
     }
     if constexpr (POROUS) {
       const double s = wave_sum(double(flux));
@@ -97,8 +108,8 @@ __global__ __launch_bounds__(kBlock) void k_init_eq(T *__restrict__ A, T *__rest
   }
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    st(A + (int64_t)i * np + p, static_cast<typename Acc<T>::type>(g[i]));
-    st(B + (int64_t)i * np + p, static_cast<typename Acc<T>::type>(g[i]));
+    st(A + pidx((int32_t)p, i), static_cast<typename Acc<T>::type>(g[i]));
+    st(B + pidx((int32_t)p, i), static_cast<typename Acc<T>::type>(g[i]));
   }
 }
 
@@ -117,11 +128,11 @@ __global__ __launch_bounds__(kBlock) void k_set_state(T *__restrict__ Pre, T *__
   for (int i = 0; i < Q; ++i)
     g[i] = id < 0 ? C(0) : C(staging[(int64_t)id * Q + i] - shift<SH>(i, rho0));
 #pragma unroll
-  for (int i = 0; i < Q; ++i) st(Pre + (int64_t)i * np + p, g[i]);
+  for (int i = 0; i < Q; ++i) st(Pre + pidx((int32_t)p, i), g[i]);
   if (id < 0) return;
   collide<SH>(g, omega, C(rho0));
 #pragma unroll
-  for (int i = 0; i < Q; ++i) st(Post + (int64_t)i * np + p, g[i]);
+  for (int i = 0; i < Q; ++i) st(Post + pidx((int32_t)p, i), g[i]);
 }
 
 // --------------------------------------------------------------- macros ----
@@ -141,7 +152,7 @@ __global__ __launch_bounds__(kBlock) void k_macros(const T *__restrict__ A, Gath
   double g[Q];
   if (direct) {
 #pragma unroll
-    for (int i = 0; i < Q; ++i) g[i] = ld(A + (int64_t)i * a.np + p);
+    for (int i = 0; i < Q; ++i) g[i] = ld(A + pidx((int32_t)p, i));
   } else if (p < a.io_begin) {
     gather<false, POROUS, SH>(A, p, p / kBlock, a, g);
   } else {
@@ -223,7 +234,7 @@ __global__ __launch_bounds__(kBlock) void k_mass_partial(const T *__restrict__ A
     if (order[p] < 0) continue;
     double q = 0.0;
 #pragma unroll
-    for (int i = 0; i < Q; ++i) q += ld(A + (int64_t)i * np + p);
+    for (int i = 0; i < Q; ++i) q += ld(A + pidx((int32_t)p, i));
     s += q;
   }
   s = wave_sum(s);
@@ -270,11 +281,19 @@ hipError_t step_impl(const LaunchCfg &cfg, const Layout &L, const DevPtrs &d, in
   const unsigned grid = (unsigned)(nb_io + nb_bulk);
   hipError_t er;
   if (e0 && (er = hipEventRecord(e0, s)) != hipSuccess) return er;
+  // byte offsets fit in 32 bits when a whole population buffer does
+  const bool narrow = kStepNarrow<T> && (uint64_t)Q * (uint64_t)L.np * sizeof(T) <= (uint64_t(1) << 32);
   if (grid > 0) {
-    if (cfg.porous)
-      k_step<T, true><<<grid, kBlock, 0, s>>>(A, B, a, d.order, n0, nb_io, nb_bulk, cfg.xcd_chunk, omega, d.acc);
-    else
-      k_step<T, false><<<grid, kBlock, 0, s>>>(A, B, a, d.order, n0, nb_io, nb_bulk, cfg.xcd_chunk, omega, d.acc);
+#define HLB_STEP(P, N) \
+  k_step<T, P, N><<<grid, kBlock, 0, s>>>(A, B, a, d.order, n0, nb_io, nb_bulk, cfg.xcd_chunk, omega, d.acc)
+    if (cfg.porous) {
+      if (narrow) HLB_STEP(true, kStepNarrow<T>);
+      else HLB_STEP(true, false);
+    } else {
+      if (narrow) HLB_STEP(false, kStepNarrow<T>);
+      else HLB_STEP(false, false);
+    }
+#undef HLB_STEP
   }
   if ((er = hipGetLastError()) != hipSuccess) return er;
   if (e1 && (er = hipEventRecord(e1, s)) != hipSuccess) return er;

@@ -301,7 +301,9 @@ hlb_status hlb_create(int64_t n, const int32_t *coords, const uint8_t *type, con
   if (!out) return fail(HLB_EINVAL, "out is null");
   *out = nullptr;
   if (!coords || !type || !nbr) return fail(HLB_EINVAL, "coords, site_type and nbr must be non-null");
-  if (n < 1 || n >= (int64_t)(1 << 30) - 4096) return fail(HLB_EINVAL, "n_sites=%lld out of range", (long long)n);
+  // positions (padding included) stay below 2^30, so that a position plus or
+  // minus np fits in int32 in the kernels
+  if (n < 1 || n >= (int64_t)(1 << 30) - 8192) return fail(HLB_EINVAL, "n_sites=%lld out of range", (long long)n);
   if (!(tau > 0.5) || !std::isfinite(tau)) return fail(HLB_EINVAL, "tau=%g must be finite and > 1/2", tau);
   if (n_iolets < 0 || (n_iolets > 0 && !iolets)) return fail(HLB_EINVAL, "bad iolet list");
   hlb_options opt;
@@ -418,7 +420,7 @@ hlb_status hlb_create(int64_t n, const int32_t *coords, const uint8_t *type, con
     pos = (pos + kGroupAlign - 1) / kGroupAlign * kGroupAlign;
   }
   L.gbeg[kGroups] = pos;
-  L.np = std::max<int64_t>(pos, kGroupAlign);
+  L.np = (std::max<int64_t>(pos, 1) + kPopTile - 1) / kPopTile * kPopTile;
   L.io_begin = L.gbeg[1];
   L.nio = L.np - L.io_begin;
   const int64_t np = L.np;
@@ -907,7 +909,7 @@ hlb_status hlb_state_save(hlb_ctx *c, void *buf) {
   if (hlb_status st = bind(c)) return st;
   StateHeader h;
   std::memset(&h, 0, sizeof(h));
-  std::memcpy(h.magic, "HLBSTAT1", 8);
+  std::memcpy(h.magic, "HLBSTAT2", 8);
   h.n_sites = c->L.n_sites; h.np = c->L.np; h.t = c->t; h.t0 = c->t0;
   h.storage = c->cfg.storage; h.cur = c->cur; h.direct = c->direct ? 1 : 0; h.m0 = c->m0;
   HIP_TRY(hipMemcpyAsync(h.acc, c->d.acc, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
@@ -924,7 +926,7 @@ hlb_status hlb_state_load(hlb_ctx *c, const void *buf) {
   if (!buf) return fail(HLB_EINVAL, "null buffer");
   StateHeader h;
   std::memcpy(&h, buf, sizeof(h));
-  if (std::memcmp(h.magic, "HLBSTAT1", 8) != 0 || h.n_sites != c->L.n_sites || h.np != c->L.np ||
+  if (std::memcmp(h.magic, "HLBSTAT2", 8) != 0 || h.n_sites != c->L.n_sites || h.np != c->L.np ||
       h.storage != c->cfg.storage)
     return fail(HLB_EINVAL, "state buffer does not match this context");
   if (hlb_status st = bind(c)) return st;
