@@ -96,11 +96,11 @@ def stored_traffic(storage, n_sites):
     p = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(p):
         return None
-    d = json.load(open(p))
-    e = d.get(storage)
-    if not e or e.get("kernel_sha") != kernel_source_hash() or e.get("n_sites") != n_sites:
-        return None
-    return e.get("bytes_per_launch")
+    sha = kernel_source_hash()
+    for e in json.load(open(p)).get("entries", []):
+        if e.get("storage") == storage and e.get("n_sites") == n_sites and e.get("kernel_sha") == sha:
+            return e.get("bytes_per_launch")
+    return None
 
 
 def run_storage(g, tables, tau, storage, steps, warmup):
