@@ -72,8 +72,10 @@ def _load():
 
 def _declare_adjoint(lib):
     P, i64, i32, d = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
-    lib.orc_adj_run.argtypes = [i64, P, P, d, d, P, i32, P, i64, i64, i64, i64, P, P, P, P]
+    lib.orc_adj_run.argtypes = [i64, P, P, d, d, P, i32, P, i64, i64, i64, i64, i32, P, P, P, P, P]
     lib.orc_adj_run.restype = ctypes.c_int
+    lib.orc_iolet_flux.argtypes = [i64, P, P, d, d, P, i32, i64, P, P]
+    lib.orc_iolet_flux.restype = ctypes.c_int
 
 
 def _p(a):
@@ -155,30 +157,47 @@ class Problem:
     def wss_sum(self, f) -> float:
         return float(_load().orc_wss_sum(self.n, _p(self.nbr), self.tau, _p(np.ascontiguousarray(f))))
 
-    def adjoint(self, f0, t0: int, nsteps: int, obj_t0: int, obj_t1: int):
-        """Reference adjoint (oracle_adjoint.c): J = sum over t in (obj_t0, obj_t1]
-        of the summed wall shear stress, and its derivatives with respect to
-        the per-step velocity-iolet table values [n_io][nsteps] and the
-        per-site porosity [n].  Keeps all nsteps+1 states in memory."""
+    def adjoint(self, f0, t0: int, nsteps: int, obj_t0: int, obj_t1: int, weights=None):
+        """Reference adjoint (oracle_adjoint.c).  J = sum over t in (obj_t0,
+        obj_t1] of the summed wall shear stress (weights None), or of
+        sum_k weights[k] Q_k(t), Q_k(t) the outflow of iolet k during the
+        update t-1 -> t (weights [n_io]).  Returns J, the derivatives with
+        respect to the per-step iolet table values [n_io][nsteps] (amplitude
+        or ghost density) and the per-site porosity [n].  Keeps all nsteps+1
+        states in memory."""
         f0 = np.ascontiguousarray(f0, dtype=np.float64)
         J = np.zeros(1)
         dA = np.zeros((max(self.n_io, 1), nsteps))
         dphi = np.zeros(self.n)
+        w = None if weights is None else np.ascontiguousarray(weights, dtype=np.float64)
         rc = _load().orc_adj_run(self.n, _p(self.coords), _p(self.nbr), self.tau, self.rho0, ctypes.byref(self.io),
-                                 self.n_io, _p(self.phi), int(t0), int(nsteps), int(obj_t0), int(obj_t1), _p(f0),
+                                 self.n_io, _p(self.phi), int(t0), int(nsteps), int(obj_t0), int(obj_t1),
+                                 0 if w is None else 1, None if w is None else _p(w), _p(f0),
                                  _p(J), _p(dA), _p(dphi))
         if rc != 0:
             raise ValueError("oracle adjoint failed")
         return float(J[0]), dA[: self.n_io], dphi
 
-    def objective(self, f0, t0: int, nsteps: int, obj_t0: int, obj_t1: int) -> float:
+    def iolet_flux(self, f, t: int) -> np.ndarray:
+        """Outflow of each iolet during the update t -> t+1 from the state f at t."""
+        Q = np.zeros(max(self.n_io, 1))
+        f = np.ascontiguousarray(f, dtype=np.float64)
+        rc = _load().orc_iolet_flux(self.n, _p(self.coords), _p(self.nbr), self.tau, self.rho0,
+                                    ctypes.byref(self.io), self.n_io, int(t), _p(f), _p(Q))
+        if rc != 0:
+            raise ValueError("bad link code")
+        return Q[: self.n_io]
+
+    def objective(self, f0, t0: int, nsteps: int, obj_t0: int, obj_t1: int, weights=None) -> float:
         """J of adjoint() by a plain forward run (no derivatives)."""
         f = np.array(f0, dtype=np.float64, copy=True)
         J = 0.0
         for s in range(nsteps):
-            self.run(f, t0 + s, 1)
             t = t0 + s + 1
-            if obj_t0 < t <= obj_t1:
+            if weights is not None and obj_t0 < t <= obj_t1:
+                J += float(np.dot(weights, self.iolet_flux(f, t - 1)))
+            self.run(f, t0 + s, 1)
+            if weights is None and obj_t0 < t <= obj_t1:
                 J += self.wss_sum(f)
         return J
 

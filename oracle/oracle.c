@@ -121,6 +121,53 @@ static void kadd(kahan *k, double v) {
   k->s = t;
 }
 
+/* The population an iolet returns to site x (coordinates xc) in direction
+ * opp(i) when the post-collision f'_i(x) = fp[i] leaves through it during the
+ * update t -> t+1; u is the site's velocity at t.
+ *   Ladd (Sec. 2.3.2): bounce-back plus -2 w_i rho c_i.U / cs^2, rho = rho0,
+ *     U taken at the link midpoint x + c_i/2;
+ *   ghost density (Sec. 2.3.2): the equilibrium at the iolet density
+ *     rho_k(t) and the site velocity projected on the iolet normal. */
+static double iolet_fill(const orc_iolet *K, const int32_t *xc, int i, int64_t t, double rho0, const double *fp,
+                         const double *u) {
+  if (K->kind == 0) {
+    const double m[3] = {xc[0] + 0.5 * C[i][0], xc[1] + 0.5 * C[i][1], xc[2] + 0.5 * C[i][2]};
+    double U[3];
+    iolet_velocity(K, m, t, U);
+    return fp[i] - 2.0 * W[i] * rho0 * cdot(i, U) / CS2;
+  }
+  const double *nk = K->normal;
+  const double un = u[0] * nk[0] + u[1] * nk[1] + u[2] * nk[2];
+  const double ug[3] = {un * nk[0], un * nk[1], un * nk[2]};
+  double fg[ORC_Q];
+  orc_equilibrium(orc_table_at(K, t), ug, fg);
+  return fg[OPP[i]];
+}
+
+int orc_iolet_flux(int64_t n, const int32_t *coords, const int32_t *nbr, double tau, double rho0,
+                   const orc_iolet *io, int32_t n_io, int64_t t, const double *f, double *Q) {
+  for (int k = 0; k < n_io; ++k) Q[k] = 0.0;
+  int bad = 0;
+  /* serial over sites: a fixed summation order, small cases only */
+  for (int64_t x = 0; x < n; ++x) {
+    const double *fx = f + ORC_Q * x;
+    double rho, u[3], fp[ORC_Q];
+    int any = 0;
+    for (int i = 0; i < ORC_Q; ++i) any |= nbr[ORC_Q * x + i] < ORC_WALL;
+    if (!any) continue;
+    orc_moments(fx, &rho, u);
+    orc_collide(fx, tau, fp);
+    for (int i = 0; i < ORC_Q; ++i) {
+      const int32_t y = nbr[ORC_Q * x + i];
+      if (y >= ORC_WALL) continue;
+      const int32_t k = -(y + 2);
+      if (k < 0 || k >= n_io) { bad = 1; continue; }
+      Q[k] += fp[i] - iolet_fill(io + k, coords + 3 * x, i, t, rho0, fp, u);
+    }
+  }
+  return bad ? -1 : 0;
+}
+
 int orc_step(int64_t n, const int32_t *coords, const int32_t *nbr, double tau, double rho0,
              const orc_iolet *io, int32_t n_io, const double *phi, int64_t t, const double *f,
              double *F, double *flux_out, int32_t *write_count) {
@@ -164,27 +211,8 @@ int orc_step(int64_t n, const int32_t *coords, const int32_t *nbr, double tau, d
         } else {
           const int32_t k = -(y + 2);
           if (k < 0 || k >= n_io) { bad = 1; continue; }
-          const orc_iolet *K = io + k;
           slot = ORC_Q * x + OPP[i];
-          if (K->kind == 0) {
-            /* Ladd (Sec. 2.3.2): bounce-back plus -2 w_i rho c_i.U / cs^2,
-             * rho = rho0, U taken at the link midpoint x + c_i/2 */
-            const double m[3] = {coords[3 * x] + 0.5 * C[i][0], coords[3 * x + 1] + 0.5 * C[i][1],
-                                 coords[3 * x + 2] + 0.5 * C[i][2]};
-            double U[3];
-            iolet_velocity(K, m, t, U);
-            val = fp[i] - 2.0 * W[i] * rho0 * cdot(i, U) / CS2;
-          } else {
-            /* ghost density (Sec. 2.3.2): the incoming population is the
-             * equilibrium at the iolet density rho_k(t) and the site velocity
-             * projected on the iolet normal */
-            const double *nk = K->normal;
-            const double un = u[0] * nk[0] + u[1] * nk[1] + u[2] * nk[2];
-            const double ug[3] = {un * nk[0], un * nk[1], un * nk[2]};
-            double fg[ORC_Q];
-            orc_equilibrium(orc_table_at(K, t), ug, fg);
-            val = fg[OPP[i]];
-          }
+          val = iolet_fill(io + k, coords + 3 * x, i, t, rho0, fp, u);
           kadd(&acc, val - fp[i]);
         }
         F[slot] = val;

@@ -74,6 +74,15 @@ int orc_step(int64_t n, const int32_t *coords, const int32_t *nbr, double tau, d
              const orc_iolet *io, int32_t n_io, const double *phi, int64_t t, const double *f,
              double *F, double *flux_out, int32_t *write_count);
 
+/* Net outflow through each iolet during the update t -> t+1 from the
+ * pre-collision state f at t (not a rule of the paper; the outlet-flux
+ * objective): Q[k] = sum over the links of iolet k of (post-collision
+ * population that leaves - population the iolet returns).  Summed over all
+ * iolets it is the mass the step loses (no porosity).  Returns 0, or -1 on
+ * a bad link code. */
+int orc_iolet_flux(int64_t n, const int32_t *coords, const int32_t *nbr, double tau, double rho0,
+                   const orc_iolet *io, int32_t n_io, int64_t t, const double *f, double *Q);
+
 /* nsteps updates starting at time t0; f holds the state at t0 on entry and at
  * t0+nsteps on return (work: scratch of n*19 doubles).  *flux_sum (may be
  * NULL) is increased by the boundary mass flux of every step. */
@@ -94,19 +103,24 @@ double orc_table_at(const orc_iolet *k, int64_t s);
 /* Ladd velocity profile per unit amplitude at point m: weight times direction. */
 void orc_iolet_profile(const orc_iolet *k, const double *m, double *P);
 
-/* Reference adjoint (oracle_adjoint.c).  Objective
- *   J = sum over t in (obj_t0, obj_t1], t0 < t <= t0 + nsteps, of the sum of
- *       WSS(x, t) over the sites with wall links,
- * WSS of the pre-collision state at t as in orc_macros.  From the state f0
- * at t0, run nsteps forward (storing every state), then the adjoint sweep.
- * Outputs: *J; dJ_dA [n_io][nsteps]: derivative with respect to the table
- * value iolet k uses at step t0+s (velocity iolets; zero for pressure ones);
- * dJ_dphi [n]: derivative with respect to each site's porosity (zero at sites
- * without wall links).  phi may be NULL (no porosity, derivative still at
- * phi = 0).  Returns 0, or -1 on a bad link code / allocation failure. */
+/* Reference adjoint (oracle_adjoint.c).  Objective, for t in (obj_t0,
+ * obj_t1] with t0 < t <= t0 + nsteps:
+ *   objective 0: J = sum over t of the sum of WSS(x, t) over the sites with
+ *                wall links (WSS of the pre-collision state at t as in
+ *                orc_macros);
+ *   objective 1: J = sum over t of sum_k weights[k] Q_k, Q_k the outflow of
+ *                iolet k during the update t-1 -> t (orc_iolet_flux).
+ * From the state f0 at t0, run nsteps forward (storing every state), then
+ * the adjoint sweep.  Outputs: *J; dJ_dtab [n_io][nsteps]: derivative with
+ * respect to the table value iolet k uses at step t0+s (the amplitude A_k of
+ * a velocity iolet, the ghost density rho_k of a pressure iolet); dJ_dphi
+ * [n]: derivative with respect to each site's porosity (zero at sites without
+ * wall links).  phi may be NULL (no porosity, derivative still at phi = 0).
+ * Returns 0, or -1 on a bad argument, link code or allocation failure. */
 int orc_adj_run(int64_t n, const int32_t *coords, const int32_t *nbr, double tau, double rho0,
                 const orc_iolet *io, int32_t n_io, const double *phi, int64_t t0, int64_t nsteps,
-                int64_t obj_t0, int64_t obj_t1, const double *f0, double *J, double *dJ_dA, double *dJ_dphi);
+                int64_t obj_t0, int64_t obj_t1, int32_t objective, const double *weights, const double *f0,
+                double *J, double *dJ_dtab, double *dJ_dphi);
 
 /* Number of OpenMP threads the oracle uses. */
 int32_t orc_threads(void);

@@ -9,7 +9,11 @@
  * followed by the scatter of eq. (3b) with the boundary rules of Sec. 2.3.
  * With mu_t = dJ/df_t (J as in oracle.h),
  *   mu_t = (dS_t/df_t)^T mu_{t+1} + dJ_t/df_t,
- *   dJ/dA_k(t) = (dS_t/dA_k)^T mu_{t+1},   dJ/dphi_x += (dS_t/dphi_x)^T mu_{t+1}.
+ *   dJ/dA_k(t) = (dS_t/dA_k)^T mu_{t+1} + dJ_t/dA_k(t),
+ *   dJ/dphi_x += (dS_t/dphi_x)^T mu_{t+1},
+ * A_k(t) the table value of iolet k (amplitude or ghost density).  The WSS
+ * objective depends on f_t only; the outflow objective of the update
+ * t -> t+1 depends on f_t and A_k(t) directly.
  * All forward states are kept in memory (no checkpointing): small cases only.
  * The Jacobians are written out as explicit 19x19 matrices.
  */
@@ -99,7 +103,7 @@ static double wss_and_grad(const double *f, const int32_t *nb, double tau, doubl
  * derivatives are added to dA_part (per thread, [n_io]) and dJ_dphi. */
 static int adj_step(int64_t n, const int32_t *coords, const int32_t *nbr, double tau, double rho0,
                     const orc_iolet *io, int32_t n_io, const double *phi, int64_t t, const double *f,
-                    const double *mu_next, double *mu_out, double *dA, double *dJ_dphi) {
+                    const double *mu_next, const double *wflux, double *mu_out, double *dA, double *dJ_dphi) {
   int bad = 0;
   int nthreads = 1;
 #ifdef _OPENMP
@@ -138,21 +142,29 @@ static int adj_step(int64_t n, const int32_t *coords, const int32_t *nbr, double
           if (k < 0 || k >= n_io) { bad = 1; continue; }
           const orc_iolet *K = io + k;
           const double m = mu_next[ORC_Q * x + LOPP[i]];
+          /* outflow objective: this link adds f'_i - value to Q_k */
+          const double wk = wflux ? wflux[k] : 0.0;
           if (K->kind == 0) {
+            /* value = f'_i + A_k(t) * (-2 w_i rho0 c_i.P / cs^2): the outflow
+             * does not depend on f'_i */
             a[i] = m;
             const double mp[3] = {coords[3 * x] + 0.5 * LC[i][0], coords[3 * x + 1] + 0.5 * LC[i][1],
                                   coords[3 * x + 2] + 0.5 * LC[i][2]};
             double P[3];
             orc_iolet_profile(K, mp, P);
             const double cP = LC[i][0] * P[0] + LC[i][1] * P[1] + LC[i][2] * P[2];
-            myA[k] += m * (-2.0 * LW[i] * rho0 * cP / CS2);
+            myA[k] += (m - wk) * (-2.0 * LW[i] * rho0 * cP / CS2);
           } else {
             /* value = f^eq_o(rho_k, ug), o = opp(i), ug = (u.n) n */
+            a[i] = wk;
             const int o = LOPP[i];
             const double *nk = K->normal;
             const double un = u[0] * nk[0] + u[1] * nk[1] + u[2] * nk[2];
             const double ug[3] = {un * nk[0], un * nk[1], un * nk[2]};
             const double rk = orc_table_at(K, t);
+            double f1[ORC_Q]; /* d value / d rho_k = f^eq_o(1, ug) */
+            orc_equilibrium(1.0, ug, f1);
+            myA[k] += (m - wk) * f1[o];
             const double cu = LC[o][0] * ug[0] + LC[o][1] * ug[1] + LC[o][2] * ug[2];
             double g[3]; /* d f^eq_o / d ug */
             for (int b = 0; b < 3; ++b) g[b] = LW[o] * rk * (3.0 * LC[o][b] + 9.0 * cu * LC[o][b] - 3.0 * ug[b]);
@@ -160,7 +172,7 @@ static int adj_step(int64_t n, const int32_t *coords, const int32_t *nbr, double
             /* d ug / d f_j = n (n . (c_j - u)) / rho */
             for (int j = 0; j < ORC_Q; ++j) {
               const double ncj = nk[0] * (LC[j][0] - u[0]) + nk[1] * (LC[j][1] - u[1]) + nk[2] * (LC[j][2] - u[2]);
-              dpre[j] += m * gn * ncj / rho;
+              dpre[j] += (m - wk) * gn * ncj / rho;
             }
           }
         }
@@ -183,7 +195,10 @@ static int adj_step(int64_t n, const int32_t *coords, const int32_t *nbr, double
 
 int orc_adj_run(int64_t n, const int32_t *coords, const int32_t *nbr, double tau, double rho0,
                 const orc_iolet *io, int32_t n_io, const double *phi, int64_t t0, int64_t nsteps,
-                int64_t obj_t0, int64_t obj_t1, const double *f0, double *J, double *dJ_dA, double *dJ_dphi) {
+                int64_t obj_t0, int64_t obj_t1, int32_t objective, const double *weights, const double *f0,
+                double *J, double *dJ_dA, double *dJ_dphi) {
+  if (objective != 0 && (objective != 1 || (n_io > 0 && !weights))) return -1;
+  const int wss = objective == 0;
   lattice_init();
   const size_t sz = (size_t)ORC_Q * (size_t)n;
   double *F = (double *)malloc(sizeof(double) * sz * (size_t)(nsteps + 1));
@@ -201,34 +216,53 @@ int orc_adj_run(int64_t n, const int32_t *coords, const int32_t *nbr, double tau
       free(F); free(mu); free(mu2); free(gr); free(dA);
       return -1;
     }
-  /* objective and its state gradients at each time in the window */
+  /* objective: WSS of the state at t, or the weighted outflow of the update
+   * t-1 -> t, for each t in the window */
   double Jsum = 0.0, Jc = 0.0;
+  double *Qk = (double *)calloc(n_io > 0 ? (size_t)n_io : 1, sizeof(double));
+  if (!Qk) {
+    free(F); free(mu); free(mu2); free(gr); free(dA);
+    return -1;
+  }
   for (int64_t s = 1; s <= nsteps; ++s) {
     const int64_t t = t0 + s;
     if (t <= obj_t0 || t > obj_t1) continue;
-    const double v = orc_wss_sum(n, nbr, tau, F + sz * s);
+    double v = 0.0;
+    if (wss) {
+      v = orc_wss_sum(n, nbr, tau, F + sz * s);
+    } else {
+      if (orc_iolet_flux(n, coords, nbr, tau, rho0, io, n_io, t - 1, F + sz * (s - 1), Qk) != 0) {
+        free(F); free(mu); free(mu2); free(gr); free(dA); free(Qk);
+        return -1;
+      }
+      for (int k = 0; k < n_io; ++k) v += weights[k] * Qk[k];
+    }
     const double y = v - Jc, tt = Jsum + y;
     Jc = (tt - Jsum) - y;
     Jsum = tt;
   }
+  free(Qk);
   *J = Jsum;
   if (dJ_dphi) memset(dJ_dphi, 0, sizeof(double) * (size_t)n);
   if (dJ_dA) memset(dJ_dA, 0, sizeof(double) * (size_t)(n_io > 0 ? n_io : 0) * (size_t)nsteps);
   /* mu = dJ/df_T */
-  if (t0 + nsteps > obj_t0 && t0 + nsteps <= obj_t1) {
+  if (wss && t0 + nsteps > obj_t0 && t0 + nsteps <= obj_t1) {
 #pragma omp parallel for schedule(static)
     for (int64_t x = 0; x < n; ++x) wss_and_grad(F + sz * nsteps + ORC_Q * x, nbr + ORC_Q * x, tau, mu + ORC_Q * x);
   }
   for (int64_t s = nsteps - 1; s >= 0; --s) {
     for (int k = 0; k < n_io; ++k) dA[k] = 0.0;
-    if (adj_step(n, coords, nbr, tau, rho0, io, n_io, phi, t0 + s, F + sz * s, mu, mu2, dA, dJ_dphi) != 0) {
+    /* the outflow of the update t0+s -> t0+s+1 counts if t0+s+1 is in the window */
+    const int flux_here = !wss && t0 + s + 1 > obj_t0 && t0 + s + 1 <= obj_t1;
+    if (adj_step(n, coords, nbr, tau, rho0, io, n_io, phi, t0 + s, F + sz * s, mu, flux_here ? weights : NULL, mu2,
+                 dA, dJ_dphi) != 0) {
       free(F); free(mu); free(mu2); free(gr); free(dA);
       return -1;
     }
     if (dJ_dA)
-      for (int k = 0; k < n_io; ++k) dJ_dA[(size_t)k * nsteps + s] = io[k].kind == 0 ? dA[k] : 0.0;
+      for (int k = 0; k < n_io; ++k) dJ_dA[(size_t)k * nsteps + s] = dA[k];
     const int64_t t = t0 + s;
-    if (s >= 1 && t > obj_t0 && t <= obj_t1) {
+    if (wss && s >= 1 && t > obj_t0 && t <= obj_t1) {
 #pragma omp parallel for schedule(static)
       for (int64_t x = 0; x < n; ++x) {
         wss_and_grad(F + sz * s + ORC_Q * x, nbr + ORC_Q * x, tau, gr + ORC_Q * x);
