@@ -231,15 +231,29 @@ typedef struct {
 } hlb_stats_t;
 hlb_status hlb_stats(hlb_ctx *ctx, hlb_stats_t *stats);
 
+/* Objective of hlb_adjoint_run (not a rule of the paper).
+ *   HLB_OBJ_WSS (default): the wall shear stress (hlb_macros' definition)
+ *     of the state at t, summed over the sites with wall links;
+ *   HLB_OBJ_IOLET_FLUX: sum_k weights[k] Q_k(t), Q_k(t) the net outflow
+ *     through iolet k during the update t-1 -> t: over the iolet's links,
+ *     the post-collision population that leaves minus the one the iolet
+ *     returns (with weight 1 on every iolet and no porosity, the mass the
+ *     step loses).
+ * weights: host, [n_iolets], copied; ignored (may be NULL) for HLB_OBJ_WSS.
+ * Errors: HLB_EINVAL (unknown kind, weights NULL or not finite). */
+enum { HLB_OBJ_WSS = 0, HLB_OBJ_IOLET_FLUX = 1 };
+hlb_status hlb_set_objective(hlb_ctx *ctx, int32_t kind, const double *weights);
+
 /* Differentiation (not a rule of the paper): the adjoint of the update.
  * From the current state at time t0, run n >= 1 steps and the reverse-time
- * sweep for the objective
- *   J = sum over t in (obj_t0, obj_t1], t0 < t <= t0 + n, of the wall shear
- *       stress (hlb_macros' definition) summed over the sites with wall links,
+ * sweep for the objective (hlb_set_objective)
+ *   J = sum over t in (obj_t0, obj_t1], t0 < t <= t0 + n, of the objective
+ *       at t,
  * with respect to
- *   dJ_dA   [n_iolets][n] (host, may be NULL): the table value A_k(t0 + s)
- *           that velocity iolet k uses in the update t0+s -> t0+s+1
- *           (zero rows for pressure iolets);
+ *   dJ_dA   [n_iolets][n] (host, may be NULL): the table value iolet k uses
+ *           in the update t0+s -> t0+s+1: the amplitude A_k(t0 + s) of a
+ *           velocity iolet, the ghost density rho_k(t0 + s) of a pressure
+ *           iolet;
  *   dJ_dphi [n_sites] (host, caller order, may be NULL): each site's
  *           porosity (hlb_set_porosity), zero at sites without wall links,
  *           evaluated at the current porosity (0 if none is set).

@@ -15,6 +15,10 @@ one reverse sweep, however many outputs the graph differentiates -- and
 ``backward`` only scales the stored gradients.  torch is used for the
 tensors; every step of the computation runs in libhlb.so.
 
+``IoletFluxObjective`` does the same for the weighted net outflow through
+the iolets, with gradients also for the per-step ghost densities of the
+pressure iolets.
+
 ``fourier_inlet(theta, n, period, base)`` builds A(s) = base + sum_k
 a_k cos(2 pi k s / period) + b_k sin(2 pi k s / period) from theta = (a, b)
 in torch, so gradients reach the Fourier coefficients through autograd.
@@ -37,20 +41,37 @@ def fourier_inlet(theta: torch.Tensor, n: int, period: float, base: float = 0.01
     return base + torch.cos(ang) @ theta[:m] + torch.sin(ang) @ theta[m:]
 
 
+def _adjoint(sim, A, R, phi, n: int, obj_t0: int, obj_t1: int, n_snap: int, kind: int, weights):
+    """Set the per-step tables (velocity rows from A, pressure rows from R if
+    given) and the porosity, run hlb_adjoint_run; returns J and the gradients
+    of A, R (or None) and phi as tensors like the inputs."""
+    info = hlb.hlb_info(sim.ctx)
+    t0 = hlb.hlb_time(sim.ctx)
+    vel = [k for k in range(info["n_iolets"]) if sim.iolet_kinds[k] == hlb.HLB_IOLET_VELOCITY]
+    pres = [k for k in range(info["n_iolets"]) if sim.iolet_kinds[k] == hlb.HLB_IOLET_PRESSURE]
+    for rows, T in ((vel, A), (pres, R)):
+        if T is None:
+            continue
+        T_h = T.detach().to("cpu", torch.float64).numpy().reshape(len(rows), n)
+        for r, k in enumerate(rows):
+            # the update t0+s -> t0+s+1 reads table[(t0 + s) mod n]
+            hlb.hlb_set_iolet_table(sim.ctx, k, np.roll(T_h[r], t0 % n))
+    hlb.hlb_set_porosity(sim.ctx, phi.detach().to("cpu", torch.float64).numpy())
+    hlb.hlb_set_objective(sim.ctx, kind, weights)
+    try:
+        J, d_tab, dphi, fw = hlb.hlb_adjoint_run(sim.ctx, n, obj_t0, obj_t1, n_snap)
+    finally:
+        hlb.hlb_set_objective(sim.ctx, hlb.HLB_OBJ_WSS)
+    dA = torch.from_numpy(d_tab[vel]).to(A.device, A.dtype).reshape(A.shape)
+    dR = None if R is None else torch.from_numpy(d_tab[pres]).to(R.device, R.dtype).reshape(R.shape)
+    return J, dA, dR, torch.from_numpy(dphi).to(phi.device, phi.dtype), fw
+
+
 class WssObjective(torch.autograd.Function):
     @staticmethod
     def forward(ctx, A, phi, sim, n: int, obj_t0: int, obj_t1: int, n_snap: int):
-        info = hlb.hlb_info(sim.ctx)
-        t0 = hlb.hlb_time(sim.ctx)
-        vel = [k for k in range(info["n_iolets"]) if sim.iolet_kinds[k] == 0]
-        A_h = A.detach().to("cpu", torch.float64).numpy().reshape(len(vel), n)
-        for row, k in enumerate(vel):
-            # the update t0+s -> t0+s+1 reads table[(t0 + s) mod n]
-            hlb.hlb_set_iolet_table(sim.ctx, k, np.roll(A_h[row], t0 % n))
-        hlb.hlb_set_porosity(sim.ctx, phi.detach().to("cpu", torch.float64).numpy())
-        J, dA, dphi, fw = hlb.hlb_adjoint_run(sim.ctx, n, obj_t0, obj_t1, n_snap)
-        ctx.save_for_backward(torch.from_numpy(dA[vel]).to(A.device, A.dtype).reshape(A.shape),
-                              torch.from_numpy(dphi).to(phi.device, phi.dtype))
+        J, dA, _, dphi, fw = _adjoint(sim, A, None, phi, n, obj_t0, obj_t1, n_snap, hlb.HLB_OBJ_WSS, None)
+        ctx.save_for_backward(dA, dphi)
         ctx.forward_steps = fw
         return torch.tensor(J, dtype=torch.float64, device=A.device)
 
@@ -58,3 +79,25 @@ class WssObjective(torch.autograd.Function):
     def backward(ctx, gJ):
         dA, dphi = ctx.saved_tensors
         return gJ * dA, gJ * dphi, None, None, None, None, None
+
+
+class IoletFluxObjective(torch.autograd.Function):
+    """``IoletFluxObjective.apply(A, R, phi, sim, n, obj_t0, obj_t1, n_snap,
+    weights)``: J = sum over t in (obj_t0, obj_t1] of sum_k weights[k] Q_k(t),
+    Q_k(t) the net outflow through iolet k during the update t-1 -> t
+    (hlb_set_objective).  Gradients with respect to A [n_velocity_iolets, n]
+    (per-step amplitudes), R [n_pressure_iolets, n] (per-step ghost
+    densities) and phi [n_sites] (porosity)."""
+
+    @staticmethod
+    def forward(ctx, A, R, phi, sim, n: int, obj_t0: int, obj_t1: int, n_snap: int, weights):
+        J, dA, dR, dphi, fw = _adjoint(sim, A, R, phi, n, obj_t0, obj_t1, n_snap, hlb.HLB_OBJ_IOLET_FLUX,
+                                       np.asarray(weights, dtype=np.float64))
+        ctx.save_for_backward(dA, dR, dphi)
+        ctx.forward_steps = fw
+        return torch.tensor(J, dtype=torch.float64, device=A.device)
+
+    @staticmethod
+    def backward(ctx, gJ):
+        dA, dR, dphi = ctx.saved_tensors
+        return gJ * dA, gJ * dR, gJ * dphi, None, None, None, None, None, None

@@ -31,8 +31,10 @@ struct AdjArgs {
   int64_t n_steps;          // row length of dA
   int64_t step;             // column of this step in dA: t-1-t0
   double *J;                // objective accumulator
-  double *dA;               // [n_io][n_steps]
+  double *dA;               // [n_io][n_steps]: iolet table-value derivatives
   double *dphi;             // [np], accumulated over the sweep
+  int objective;            // HLB_OBJ_WSS or HLB_OBJ_IOLET_FLUX
+  const double *w;          // [n_io] iolet-flux weights
 };
 
 // (dM/dg)^T w for M(g) = f^eq(rho(g), u(g)):
@@ -100,7 +102,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_collide(AdjArgs A) {
     }
     // objective: wall shear stress of g and its gradient (definition of k_macros)
     const double nn = sqrt(nx * nx + ny * ny + nz * nz);
-    if (A.in_window && any && nn > 0.0) {
+    if (A.objective == HLB_OBJ_WSS && A.in_window && any && nn > 0.0) {
       nx /= nn;
       ny /= nn;
       nz /= nn;
@@ -138,8 +140,23 @@ __global__ __launch_bounds__(kBlock) void k_adj_collide(AdjArgs A) {
       }
     }
     // parameter derivatives from the complete nu_t: porosity at wall links,
-    // amplitude at Ladd links
-    double dphi = 0.0;
+    // the table value (amplitude or ghost density) at iolet links.  With the
+    // iolet-flux objective the update t-1 -> t adds, per iolet link,
+    // w_k (leaving population - filled value) to J, and -w_k times the
+    // filled value's table derivative to that derivative.
+    const bool flux = A.objective == HLB_OBJ_IOLET_FLUX && A.in_window;
+    double ox = 0.0, oy = 0.0, oz = 0.0;  // velocity at t-1 (pressure rule)
+    if (!bulk) {
+      double s[Q];
+#pragma unroll
+      for (int i = 0; i < Q; ++i) s[i] = A.S[pidx((int32_t)p, i)];
+      double sdr, srho, sjx, sjy, sjz;
+      moments<false>(s, 0.0, sdr, srho, sjx, sjy, sjz);
+      ox = sjx / srho;
+      oy = sjy / srho;
+      oz = sjz / srho;
+    }
+    double dphi = 0.0, q = 0.0;
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
       const int32_t c = code[i - 1];
@@ -148,11 +165,24 @@ __global__ __launch_bounds__(kBlock) void k_adj_collide(AdjArgs A) {
         dphi += nu[i] * (wgt<double>(i) * a.rho0 - back);
       } else if (c < HLB_LINK_WALL) {
         const int k = -c - 2;
-        if (a.io[k].kind == HLB_IOLET_VELOCITY)
-          atomicAdd(A.dA + (int64_t)k * A.n_steps + A.step,
-                    nu[i] * a.corr[(int64_t)(i - 1) * a.nio + (p - a.io_begin)]);
+        const IoletDev K = a.io[k];
+        const double val = a.tables[K.tab_off + a.t % K.tab_len];
+        const double wk = flux ? A.w[k] : 0.0;
+        double coef, out;  // d(filled value)/d(table value); outflow of the link
+        if (K.kind == HLB_IOLET_VELOCITY) {
+          coef = a.corr[(int64_t)(i - 1) * a.nio + (p - a.io_begin)];
+          out = -coef * val;
+        } else {
+          const double un = ox * K.n[0] + oy * K.n[1] + oz * K.n[2];
+          const double gx = un * K.n[0], gy = un * K.n[1], gz = un * K.n[2];
+          coef = s_eq<false>(i, 0.0, 1.0, gx, gy, gz, 1.5 * (gx * gx + gy * gy + gz * gz));
+          out = A.S[pidx((int32_t)p, opp(i))] - val * coef;
+        }
+        atomicAdd(A.dA + (int64_t)k * A.n_steps + A.step, (nu[i] - wk) * coef);
+        q += wk * out;
       }
     }
+    if (flux) jsum = q;
     A.dphi[p] += dphi;
 #pragma unroll
     for (int i = 0; i < Q; ++i) A.nu[pidx((int32_t)p, i)] = nu[i];
@@ -167,6 +197,10 @@ __global__ __launch_bounds__(kBlock) void k_adj_stream(AdjArgs A) {
   const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (p >= a.np || A.order[p] < 0) return;
   const double ph = POROUS ? a.phi[p] : 0.0;
+  // iolet-flux objective: a population leaving through a pressure iolet adds
+  // w_k to its own adjoint (the fill does not depend on it), and the fill's
+  // dependence on u enters with weight (nu - w_k)
+  const bool flux = A.objective == HLB_OBJ_IOLET_FLUX && A.in_window;
   double m[Q];
   bool pressure = false;
   m[0] = A.nu[pidx((int32_t)p, 0)];
@@ -181,7 +215,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_stream(AdjArgs A) {
     } else if (a.io[-c - 2].kind == HLB_IOLET_VELOCITY) {
       m[i] = A.nu[pidx((int32_t)p, opp(i))];
     } else {
-      m[i] = 0.0;  // replaced by the ghost-density equilibrium
+      m[i] = flux ? A.w[-c - 2] : 0.0;  // replaced by the ghost-density equilibrium
       pressure = true;
     }
   }
@@ -207,7 +241,8 @@ __global__ __launch_bounds__(kBlock) void k_adj_stream(AdjArgs A) {
       const double dx = wgt<double>(o) * rk * (3.0 * cx(o) + 9.0 * cu * cx(o) - 3.0 * gx);
       const double dy = wgt<double>(o) * rk * (3.0 * cy(o) + 9.0 * cu * cy(o) - 3.0 * gy);
       const double dz = wgt<double>(o) * rk * (3.0 * cz(o) + 9.0 * cu * cz(o) - 3.0 * gz);
-      const double coef = A.nu[pidx((int32_t)p, o)] * (dx * K.n[0] + dy * K.n[1] + dz * K.n[2]) / rho;
+      const double wk = flux ? A.w[-c - 2] : 0.0;
+      const double coef = (A.nu[pidx((int32_t)p, o)] - wk) * (dx * K.n[0] + dy * K.n[1] + dz * K.n[2]) / rho;
 #pragma unroll
       for (int j = 0; j < Q; ++j)
         m[j] += coef * (K.n[0] * (cx(j) - ux) + K.n[1] * (cy(j) - uy) + K.n[2] * (cz(j) - uz));
@@ -240,6 +275,8 @@ hipError_t launch_adjoint_step(const LaunchCfg &cfg, const Layout &L, const DevP
   A.J = b.J;
   A.dA = b.dA;
   A.dphi = b.dphi;
+  A.objective = b.objective;
+  A.w = b.w;
   const unsigned grid = blocks_of(L.np);
   if (cfg.porous) {
     k_adj_collide<true><<<grid, kBlock, 0, s>>>(A);

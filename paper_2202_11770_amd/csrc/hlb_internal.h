@@ -106,10 +106,12 @@ struct AdjBuffers {
   double *J = nullptr;        // objective accumulator
   double *dA = nullptr;       // [n_iolets][n_steps]
   double *dphi = nullptr;     // [np] porosity derivative per position
+  int32_t objective = HLB_OBJ_WSS;
+  double *w = nullptr;        // [n_iolets] iolet-flux weights (device)
 };
 // Adjoint of the update (t-1 -> t): buffer `src` holds s_{t-1}; b.mu holds
 // mu_t on entry and mu_{t-1} on return; accumulates J (if in_window), the
-// Ladd amplitude derivatives into column `step` of dA and the porosity
+// iolet table-value derivatives into column `step` of dA and the porosity
 // derivatives.
 hipError_t launch_adjoint_step(const LaunchCfg &cfg, const Layout &L, const DevPtrs &d, int src, int64_t t,
                                const AdjBuffers &b, int in_window, int64_t n_steps, int64_t step,

@@ -185,7 +185,7 @@ void free_all(hlb_ctx *c) {
   F(c->d.phi); F(c->d.acc); F(c->d.partial); F(c->d.io_scratch);
   for (auto &s : c->snaps) { F(s.f[0]); F(s.f[1]); F(s.acc); }
   c->snaps.clear();
-  F(c->adj.mu); F(c->adj.nu); F(c->adj.push); F(c->adj.J); F(c->adj.dA); F(c->adj.dphi);
+  F(c->adj.mu); F(c->adj.nu); F(c->adj.push); F(c->adj.J); F(c->adj.dA); F(c->adj.dphi); F(c->adj.w);
   for (void *q : c->adj_slots) F(q);
   c->adj_slots.clear();
   c->adj = AdjBuffers();
@@ -652,6 +652,29 @@ hlb_status hlb_set_porosity(hlb_ctx *c, const double *phi) {
   HIP_TRY(hipStreamSynchronize(c->stream));
   HIP_TRY(hipMemcpy(c->d.phi, h.data(), np * sizeof(double), hipMemcpyHostToDevice));
   c->cfg.porous = true;
+  return HLB_OK;
+}
+
+hlb_status hlb_set_objective(hlb_ctx *c, int32_t kind, const double *weights) {
+  if (hlb_status st = check_ctx(c)) return st;
+  if (kind == HLB_OBJ_WSS) {
+    c->adj.objective = HLB_OBJ_WSS;
+    return HLB_OK;
+  }
+  if (kind != HLB_OBJ_IOLET_FLUX) return fail(HLB_EINVAL, "unknown objective kind %d", (int)kind);
+  const int64_t nio = (int64_t)c->iolets.size();
+  if (nio > 0 && !weights) return fail(HLB_EINVAL, "the iolet-flux objective needs weights");
+  for (int64_t k = 0; k < nio; ++k)
+    if (!std::isfinite(weights[k])) return fail(HLB_EINVAL, "weights[%lld] is not finite", (long long)k);
+  if (hlb_status st = bind(c)) return st;
+  if (!c->adj.w) {
+    void *p = nullptr;
+    if (hlb_status st = dev_alloc(c, &p, (size_t)std::max<int64_t>(nio, 1) * sizeof(double))) return st;
+    c->adj.w = static_cast<double *>(p);
+  }
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  if (nio > 0) HIP_TRY(hipMemcpy(c->adj.w, weights, (size_t)nio * sizeof(double), hipMemcpyHostToDevice));
+  c->adj.objective = HLB_OBJ_IOLET_FLUX;
   return HLB_OK;
 }
 

@@ -26,6 +26,7 @@ STATUS_NAMES = {0: "HLB_OK", -1: "HLB_EINVAL", -2: "HLB_ENOMEM", -3: "HLB_EDEVIC
 HLB_F64, HLB_F32_SHIFTED, HLB_F16_SHIFTED = 0, 1, 2
 STORAGE = {"f64": HLB_F64, "f32": HLB_F32_SHIFTED, "f16": HLB_F16_SHIFTED}
 HLB_ORDER_INPUT, HLB_ORDER_LEX, HLB_ORDER_MORTON, HLB_ORDER_BRICK = 0, 1, 2, 3
+HLB_IOLET_VELOCITY, HLB_IOLET_PRESSURE = 0, 1
 ORDER = {"input": 0, "lex": 1, "morton": 2, "brick": 3}
 Q = 19
 
@@ -91,6 +92,7 @@ _SIGS = {
     "hlb_state_load": [_P, _P],
     "hlb_sync": [_P],
     "hlb_copy_bandwidth": [_i64, _i32, ctypes.POINTER(_d)],
+    "hlb_set_objective": [_P, _i32, _P],
     "hlb_adjoint_run": [_P, _i64, _i64, _i64, _i32, _P, _P, _P, ctypes.POINTER(_i64)],
     "hlb_last_error": [],
 }
@@ -313,8 +315,21 @@ def hlb_sync(ctx):
     _check(load().hlb_sync(ctx), "hlb_sync")
 
 
+HLB_OBJ_WSS = 0
+HLB_OBJ_IOLET_FLUX = 1
+
+
+def hlb_set_objective(ctx, kind: int, weights=None):
+    """Objective of hlb_adjoint_run: HLB_OBJ_WSS, or HLB_OBJ_IOLET_FLUX with
+    per-iolet weights [n_iolets]."""
+    w, wp = (None, None) if weights is None else _host(weights, np.float64)
+    _check(load().hlb_set_objective(ctx, int(kind), wp), "hlb_set_objective")
+
+
 def hlb_adjoint_run(ctx, n: int, obj_t0: int, obj_t1: int, n_snap: int, want_dA=True, want_dphi=True):
-    """Returns (J, dJ_dA [n_iolets][n] or None, dJ_dphi [n_sites] or None, forward_steps)."""
+    """Returns (J, dJ_dA [n_iolets][n] or None, dJ_dphi [n_sites] or None, forward_steps).
+    Row k of dJ_dA: the amplitude (velocity iolet) or ghost density (pressure
+    iolet) iolet k uses in each of the n updates."""
     info = hlb_info(ctx)
     nio = info["n_iolets"]
     J = np.zeros(1)

@@ -129,3 +129,4 @@ def test_null_arguments():
     assert lib.hlb_mass_balance(None, None, None) == hlb.HLB_EINVAL
     assert lib.hlb_destroy(None) == hlb.HLB_OK
     assert lib.hlb_time(None, None) == hlb.HLB_EINVAL
+    assert lib.hlb_set_objective(None, 0, None) == hlb.HLB_EINVAL

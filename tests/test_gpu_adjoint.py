@@ -3,7 +3,14 @@ central finite differences of the GPU forward objective.
 
 Objective: J = sum over t in the window of the wall shear stress summed over
 the sites with wall links; parameters: per-step inlet amplitudes (through 32
-Fourier coefficients in the full case) and per-wall-site porosity.
+Fourier coefficients in the full case), per-step outlet ghost densities and
+per-wall-site porosity.
+
+The outlet density varies slightly around rho0 in the cases compared with
+the oracle: at exactly rho0, a flow started from rest leaves sites whose
+tangential traction is exactly zero, where the WSS magnitude has a kink; the
+ghost-density derivative there depends on rounding (a 1e-14 change of the
+outlet density moves it by ~10% in the oracle itself).
 """
 import math
 import sys
@@ -35,7 +42,8 @@ def _small_case(nsteps=60, seed=4):
     b = rng.uniform(-1, 1, 4) * 0.002 / np.arange(1, 5)
     A = 0.01 + sum(a[k] * np.cos(2 * np.pi * (k + 1) * s / nsteps) + b[k] * np.sin(2 * np.pi * (k + 1) * s / nsteps)
                    for k in range(4))
-    tables = [A if io.kind == G.VELOCITY else np.array([1.0]) for io in g.iolets]
+    R = 1.0 + 0.001 * np.sin(2 * np.pi * s / nsteps)
+    tables = [A if io.kind == G.VELOCITY else R.copy() for io in g.iolets]
     phi = np.zeros(g.n)
     ws = g.wall_sites()
     phi[ws] = np.random.default_rng(40).uniform(0, 1, ws.size)
@@ -87,8 +95,9 @@ def test_adjoint_matches_oracle_small():
     Jr, dAr, dphir = P.adjoint(P.init(), 0, nsteps, w0, w1)
     sim = _gpu_sim(g, tau, tables, phi)
     J, dA, dphi, fw = hlb.hlb_adjoint_run(sim.ctx, nsteps, w0, w1, 4)
-    say(f"small adjoint: J {J:.6e} vs {Jr:.6e}; dA rel {rel(dA, dAr):.2e}; dphi rel {rel(dphi, dphir):.2e}; "
-        f"forward steps {fw}")
+    say(f"small adjoint: J {J:.6e} vs {Jr:.6e}; table rows rel {rel(dA, dAr):.2e} "
+        f"({', '.join('%.2e' % rel(dA[k], dAr[k]) for k in range(len(g.iolets)))}); "
+        f"dphi rel {rel(dphi, dphir):.2e}; forward steps {fw}")
     assert abs(J - Jr) <= 1e-12 * abs(Jr)
     assert rel(dA, dAr) <= 1e-10
     assert rel(dphi, dphir) <= 1e-10
@@ -229,7 +238,8 @@ def test_c4_reduced_vs_oracle_adjoint():
     g, theta0, phi0, ws = _c4()
     n, w0, w1, tau = 300, 250, 300, 0.8
     A = _inlet_np(theta0, n, 3000.0)
-    tables = [A if io.kind == G.VELOCITY else np.array([1.0]) for io in g.iolets]
+    R = 1.0 + 0.001 * np.sin(2 * np.pi * np.arange(n) / n)
+    tables = [A if io.kind == G.VELOCITY else R for io in g.iolets]
     P = oracle.Problem(g, tau, tables=tables, phi=phi0)
     t = time.time()
     Jr, dAr, dphir = P.adjoint(P.init(), 0, n, w0, w1)
