@@ -103,11 +103,11 @@ def stored_traffic(storage, n_sites):
     return None
 
 
-def run_storage(g, tables, tau, storage, steps, warmup):
+def run_storage(g, tables, tau, storage, steps, warmup, scheme="pull"):
     import torch
     from paper_2202_11770_amd import hlb
     t0 = time.time()
-    sim = hlb.Simulation.create(g, tau, storage=storage, tables=tables)
+    sim = hlb.Simulation.create(g, tau, storage=storage, tables=tables, scheme=scheme)
     info = sim.info()
     log(f"{storage}: context created in {time.time() - t0:.1f}s, {info['device_bytes'] / 2**30:.1f} GiB on the device")
     sim.step(warmup)
@@ -218,6 +218,8 @@ def main():
     ap.add_argument("--storages", default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-copy", action="store_true")
+    ap.add_argument("--schemes", default="pull",
+                    help="update orders to time: pull (the headline), and push for the A/B")
     ap.add_argument("--compare-steps", type=int, default=0,
                     help="also run every storage for this many steps from rest and report the "
                          "FP32/FP16 errors against the FP64 GPU run")
@@ -245,6 +247,17 @@ def main():
             f"({time.time() - t1:.1f}s)")
     main_st = args.storages.split(",")[0]
     R = results[main_st]
+    ab = {}
+    for sch in [x for x in args.schemes.split(",") if x and x != "pull"]:
+        ab[sch] = {}
+        for st in args.storages.split(","):
+            r = run_storage(g, tables, tau, st, args.steps, args.warmup, scheme=sch)
+            ab[sch][st] = {"mlups": round(r["mlups"], 1), "kernel_ms": round(r["kernel_ms"], 5),
+                           "kernel_gbs": round(r["kernel_gbs"], 1), "frac": round(r["frac"], 4),
+                           "vs_pull": round(r["mlups"] / results[st]["mlups"], 3),
+                           "mass_residual_rel": r["mass_residual_rel"]}
+            log(f"{sch} {st}: {r['mlups']:.0f} MLUPS, step kernel {r['kernel_ms']:.3f} ms = {r['kernel_gbs']:.0f} GB/s "
+                f"({100 * r['frac']:.1f}%), {ab[sch][st]['vs_pull']:.3f}x pull")
     copy_gbs = None if args.no_copy else round(copy_ceiling(), 1)
     if copy_gbs:
         log(f"plain copy: {copy_gbs:.0f} GB/s")
@@ -287,6 +300,8 @@ def main():
     }
     if compare is not None:
         out["errors_vs_f64_gpu"] = {"steps": args.compare_steps, **compare}
+    if ab:
+        out["schemes"] = ab
     print(json.dumps(out), flush=True)
 
 

@@ -121,7 +121,17 @@ typedef struct {
                           storage only; 72 more bytes per site); default 0 */
   double rho0;         /* reference density (default 1.0) */
   int64_t max_device_bytes; /* 0: no limit; otherwise HLB_ENOMEM above it */
+  int32_t scheme;      /* HLB_SCHEME_PULL (default) or HLB_SCHEME_PUSH */
 } hlb_options;
+
+/* Order of the fused update (Sec. 3.2 implements push and names pull as
+ * future work).  PULL: each site gathers its populations from its
+ * neighbours' post-collision values, collides and stores the result (the
+ * buffers hold post-collision states).  PUSH: each site collides its own
+ * pre-collision state and scatters the results to the neighbours that
+ * receive them (the buffers hold pre-collision states).  Both compute the
+ * same update; hlb_adjoint_run needs PULL. */
+enum { HLB_SCHEME_PULL = 0, HLB_SCHEME_PUSH = 1 };
 
 /* Fill *opt with the defaults. */
 hlb_status hlb_default_options(hlb_options *opt);
@@ -216,6 +226,7 @@ typedef struct {
   int64_t n_iolets;         /* iolets given to hlb_create */
   int32_t adjoint;          /* adjoint tables built (opt.adjoint) */
   int32_t porous;           /* a porosity field is set */
+  int32_t scheme;           /* hlb_scheme of the context */
 } hlb_info_t;
 hlb_status hlb_info(const hlb_ctx *ctx, hlb_info_t *info);
 

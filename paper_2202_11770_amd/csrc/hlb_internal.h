@@ -76,6 +76,7 @@ struct LaunchCfg {
   double rho0 = 1.0;
   int xcd_chunk = 0;  // blocks per XCD chunk (0: plain block order)
   bool porous = false;
+  int scheme = HLB_SCHEME_PULL;
 };
 
 // ---- launchers (hlb_kernels.hip); all asynchronous on `s` ----

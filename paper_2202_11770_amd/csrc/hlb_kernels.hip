@@ -82,6 +82,48 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kStepWav
   }
 }
 
+// One step in push order (the paper's implementation; the A/B partner of
+// k_step): buffers hold the pre-collision state f(t); every site reads its
+// own 19 values (coalesced), collides and scatters (scatter()).  Same block
+// layout, XCD remap and occupancy as k_step.
+template <typename T, bool POROUS, bool NARROW>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kStepWaves<T>, 8))) void k_step_push(
+    const T *__restrict__ A, T *__restrict__ B, GatherArgs a, const int32_t *__restrict__ order, int64_t n0,
+    int64_t nb_io, int64_t nb_bulk, int xcd_chunk, typename Acc<T>::type omega, double *acc) {
+  using C = typename Acc<T>::type;
+  constexpr bool SH = kShifted<T>;
+  const int64_t b = blockIdx.x;
+  C flux = 0;
+  if (b < nb_io) {
+    const int64_t p = a.io_begin + b * kBlock + threadIdx.x;
+    if (p < a.np && order[p] >= 0) {
+      C f[Q];
+#pragma unroll
+      for (int i = 0; i < Q; ++i) f[i] = ld(at<NARROW>(A, (int32_t)p, i));
+      C dr, rho, jx, jy, jz;
+      moments<SH>(f, C(a.rho0), dr, rho, jx, jy, jz);
+      collide<SH>(f, omega, C(a.rho0));
+      flux = scatter<true, POROUS, SH, NARROW>(B, p, 0, a, f, jx / rho, jy / rho, jz / rho);
+    }
+    const double s = wave_sum(double(flux));
+    if ((threadIdx.x & 63) == 0 && s != 0.0) atomicAdd(acc, s);
+  } else {
+    const int64_t blk = block_id(b - nb_io, nb_bulk, xcd_chunk);
+    const int64_t p = blk * kBlock + threadIdx.x;
+    if (p < n0) {
+      C f[Q];
+#pragma unroll
+      for (int i = 0; i < Q; ++i) f[i] = ld(at<NARROW>(A, (int32_t)p, i));
+      collide<SH>(f, omega, C(a.rho0));
+      flux = scatter<false, POROUS, SH, NARROW>(B, p, blk, a, f, C(0), C(0), C(0));
+    }
+    if constexpr (POROUS) {
+      const double s = wave_sum(double(flux));
+      if ((threadIdx.x & 63) == 0 && s != 0.0) atomicAdd(acc, s);
+    }
+  }
+}
+
 // ------------------------------------------------------- init / state ----
 
 template <typename T>
@@ -284,8 +326,15 @@ hipError_t step_impl(const LaunchCfg &cfg, const Layout &L, const DevPtrs &d, in
   // byte offsets fit in 32 bits when a whole population buffer does
   const bool narrow = kStepNarrow<T> && (uint64_t)Q * (uint64_t)L.np * sizeof(T) <= (uint64_t(1) << 32);
   if (grid > 0) {
-#define HLB_STEP(P, N) \
-  k_step<T, P, N><<<grid, kBlock, 0, s>>>(A, B, a, d.order, n0, nb_io, nb_bulk, cfg.xcd_chunk, omega, d.acc)
+#define HLB_STEP(P, N)                                                                                    \
+  do {                                                                                                  \
+    if (cfg.scheme == HLB_SCHEME_PUSH)                                                                  \
+      k_step_push<T, P, N><<<grid, kBlock, 0, s>>>(A, B, a, d.order, n0, nb_io, nb_bulk, cfg.xcd_chunk, \
+                                                   omega, d.acc);                                       \
+    else                                                                                                \
+      k_step<T, P, N><<<grid, kBlock, 0, s>>>(A, B, a, d.order, n0, nb_io, nb_bulk, cfg.xcd_chunk, omega, \
+                                              d.acc);                                                   \
+  } while (0)
     if (cfg.porous) {
       if (narrow) HLB_STEP(true, kStepNarrow<T>);
       else HLB_STEP(true, false);

@@ -292,6 +292,7 @@ hlb_status hlb_default_options(hlb_options *opt) {
   opt->adjoint = 0;
   opt->rho0 = 1.0;
   opt->max_device_bytes = 0;
+  opt->scheme = HLB_SCHEME_PULL;
   return HLB_OK;
 }
 
@@ -316,6 +317,8 @@ hlb_status hlb_create(int64_t n, const int32_t *coords, const uint8_t *type, con
       opt.xcd_remap > (1 << 20))
     return fail(HLB_EINVAL, "bad options");
   if (opt.adjoint && opt.storage != HLB_F64) return fail(HLB_EINVAL, "the adjoint needs FP64 storage");
+  if (opt.scheme != HLB_SCHEME_PULL && opt.scheme != HLB_SCHEME_PUSH) return fail(HLB_EINVAL, "bad scheme %d", opt.scheme);
+  if (opt.adjoint && opt.scheme != HLB_SCHEME_PULL) return fail(HLB_EINVAL, "the adjoint needs the pull scheme");
   for (int k = 0; k < n_iolets; ++k) {
     const hlb_iolet &I = iolets[k];
     if (I.kind != HLB_IOLET_VELOCITY && I.kind != HLB_IOLET_PRESSURE) return fail(HLB_EINVAL, "iolet %d: bad kind", k);
@@ -385,6 +388,7 @@ hlb_status hlb_create(int64_t n, const int32_t *coords, const uint8_t *type, con
   c->cfg.rho0 = opt.rho0;
   c->cfg.xcd_chunk = opt.xcd_remap;
   c->cfg.porous = false;
+  c->cfg.scheme = opt.scheme;
   c->order = opt.order;
   c->max_bytes = opt.max_device_bytes;
   c->iolets.assign(iolets, iolets + n_iolets);
@@ -706,6 +710,20 @@ hlb_status hlb_init_equilibrium(hlb_ctx *c, const double *rho, const double *u, 
   return reset_balance(c);
 }
 
+// The buffer and mode the macros of the current state are read from: pull
+// re-gathers the previous post-collision buffer (or reads the current
+// pre-collision one right after init/set_state); push reads its current
+// pre-collision buffer directly.
+static void macro_source(const hlb_ctx *c, int *src, bool *direct) {
+  if (c->cfg.scheme == HLB_SCHEME_PUSH) {
+    *src = c->cur;
+    *direct = true;
+  } else {
+    *src = 1 - c->cur;
+    *direct = c->direct;
+  }
+}
+
 hlb_status hlb_step(hlb_ctx *c, int64_t n) {
   if (hlb_status st = check_ctx(c)) return st;
   if (n < 0) return fail(HLB_EINVAL, "n < 0");
@@ -734,7 +752,10 @@ hlb_status hlb_macros_device(hlb_ctx *c, void *rho, void *u, void *wss) {
   if (hlb_status st = check_ctx(c)) return st;
   if (hlb_status st = bind(c)) return st;
   if (!rho && !u && !wss) return HLB_OK;
-  HIP_TRY(launch_macros(c->cfg, c->L, c->d, 1 - c->cur, c->direct, c->t - 1, static_cast<double *>(rho),
+  int src;
+  bool direct;
+  macro_source(c, &src, &direct);
+  HIP_TRY(launch_macros(c->cfg, c->L, c->d, src, direct, c->t - 1, static_cast<double *>(rho),
                         static_cast<double *>(u), static_cast<double *>(wss), nullptr, c->stream));
   return HLB_OK;
 }
@@ -746,7 +767,10 @@ hlb_status hlb_macros(hlb_ctx *c, double *rho, double *u, double *wss) {
   const int64_t n = c->L.n_sites;
   if (hlb_status st = ensure_staging(c, 5 * n)) return st;
   double *dr = c->d.io_scratch, *du = dr + n, *dw = du + 3 * n;
-  HIP_TRY(launch_macros(c->cfg, c->L, c->d, 1 - c->cur, c->direct, c->t - 1, rho ? dr : nullptr, u ? du : nullptr,
+  int src;
+  bool direct;
+  macro_source(c, &src, &direct);
+  HIP_TRY(launch_macros(c->cfg, c->L, c->d, src, direct, c->t - 1, rho ? dr : nullptr, u ? du : nullptr,
                         wss ? dw : nullptr, nullptr, c->stream));
   if (rho) HIP_TRY(hipMemcpyAsync(rho, dr, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   if (u) HIP_TRY(hipMemcpyAsync(u, du, 3 * n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
@@ -763,8 +787,11 @@ hlb_status hlb_get_state(hlb_ctx *c, double *f) {
   if (!f) return fail(HLB_EINVAL, "f is null");
   if (hlb_status st = bind(c)) return st;
   if (hlb_status st = ensure_staging(c, Q * c->L.n_sites)) return st;
-  HIP_TRY(launch_macros(c->cfg, c->L, c->d, 1 - c->cur, c->direct, c->t - 1, nullptr, nullptr, nullptr,
-                        c->d.io_scratch, c->stream));
+  int src;
+  bool direct;
+  macro_source(c, &src, &direct);
+  HIP_TRY(launch_macros(c->cfg, c->L, c->d, src, direct, c->t - 1, nullptr, nullptr, nullptr, c->d.io_scratch,
+                        c->stream));
   HIP_TRY(hipMemcpyAsync(f, c->d.io_scratch, (size_t)c->L.n_sites * Q * sizeof(double), hipMemcpyDeviceToHost,
                          c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
@@ -781,10 +808,11 @@ hlb_status hlb_set_state(hlb_ctx *c, const double *f, int64_t t) {
   if (hlb_status st = bind(c)) return st;
   if (hlb_status st = ensure_staging(c, Q * n)) return st;
   HIP_TRY(hipMemcpyAsync(c->d.io_scratch, f, (size_t)n * Q * sizeof(double), hipMemcpyHostToDevice, c->stream));
-  // buffer 1 := pre-collision f(t), buffer 0 := its collision
+  // buffer 1 := pre-collision f(t), buffer 0 := its collision; a pull step
+  // reads the collided buffer, a push step the pre-collision one
   HIP_TRY(launch_set_state(c->cfg, c->L, c->d, 1, c->d.io_scratch, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
-  c->cur = 0;
+  c->cur = c->cfg.scheme == HLB_SCHEME_PUSH ? 1 : 0;
   c->direct = true;
   c->t = t;
   return reset_balance(c);
@@ -825,6 +853,7 @@ hlb_status hlb_info(const hlb_ctx *c, hlb_info_t *info) {
   info->n_iolets = (int64_t)c->iolets.size();
   info->adjoint = c->adj.push ? 1 : 0;
   info->porous = c->cfg.porous ? 1 : 0;
+  info->scheme = c->cfg.scheme;
   info->device_bytes = c->dev_bytes;
   return HLB_OK;
 }
@@ -914,7 +943,7 @@ namespace {
 struct StateHeader {
   char magic[8];
   int64_t n_sites, np, t, t0;
-  int32_t storage, cur, direct, pad;
+  int32_t storage, cur, direct, scheme;
   double m0;
   double acc[4];
 };
@@ -935,6 +964,7 @@ hlb_status hlb_state_save(hlb_ctx *c, void *buf) {
   std::memcpy(h.magic, "HLBSTAT2", 8);
   h.n_sites = c->L.n_sites; h.np = c->L.np; h.t = c->t; h.t0 = c->t0;
   h.storage = c->cfg.storage; h.cur = c->cur; h.direct = c->direct ? 1 : 0; h.m0 = c->m0;
+  h.scheme = c->cfg.scheme;
   HIP_TRY(hipMemcpyAsync(h.acc, c->d.acc, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   char *b = static_cast<char *>(buf);
   HIP_TRY(hipMemcpyAsync(b + sizeof(h), c->d.f[0], buf_bytes(c), hipMemcpyDeviceToHost, c->stream));
@@ -950,7 +980,7 @@ hlb_status hlb_state_load(hlb_ctx *c, const void *buf) {
   StateHeader h;
   std::memcpy(&h, buf, sizeof(h));
   if (std::memcmp(h.magic, "HLBSTAT2", 8) != 0 || h.n_sites != c->L.n_sites || h.np != c->L.np ||
-      h.storage != c->cfg.storage)
+      h.storage != c->cfg.storage || h.scheme != c->cfg.scheme)
     return fail(HLB_EINVAL, "state buffer does not match this context");
   if (hlb_status st = bind(c)) return st;
   const char *b = static_cast<const char *>(buf);
@@ -1053,7 +1083,7 @@ extern "C" hlb_status hlb_adjoint_run(hlb_ctx *c, int64_t n, int64_t obj_t0, int
                                       double *J, double *dJ_dA, double *dJ_dphi, int64_t *forward_steps) {
   if (hlb_status st = check_ctx(c)) return st;
   if (n < 1 || n_snap < 1 || n_snap > 4096 || !J) return fail(HLB_EINVAL, "need n >= 1, 1 <= n_snap <= 4096, J");
-  if (c->cfg.storage != HLB_F64 || !c->adj.push)
+  if (c->cfg.storage != HLB_F64 || !c->adj.push || c->cfg.scheme != HLB_SCHEME_PULL)
     return fail(HLB_ESTATE, "the adjoint needs FP64 storage and opt.adjoint = 1 at creation");
   if (hlb_status st = bind(c)) return st;
   const int64_t np = c->L.np, nio = (int64_t)c->iolets.size();

@@ -27,6 +27,8 @@ HLB_F64, HLB_F32_SHIFTED, HLB_F16_SHIFTED = 0, 1, 2
 STORAGE = {"f64": HLB_F64, "f32": HLB_F32_SHIFTED, "f16": HLB_F16_SHIFTED}
 HLB_ORDER_INPUT, HLB_ORDER_LEX, HLB_ORDER_MORTON, HLB_ORDER_BRICK = 0, 1, 2, 3
 HLB_IOLET_VELOCITY, HLB_IOLET_PRESSURE = 0, 1
+HLB_SCHEME_PULL, HLB_SCHEME_PUSH = 0, 1
+SCHEME = {"pull": HLB_SCHEME_PULL, "push": HLB_SCHEME_PUSH}
 ORDER = {"input": 0, "lex": 1, "morton": 2, "brick": 3}
 Q = 19
 
@@ -44,7 +46,8 @@ class hlb_iolet(ctypes.Structure):
 
 class hlb_options(ctypes.Structure):
     _fields_ = [("storage", ctypes.c_int32), ("order", ctypes.c_int32), ("xcd_remap", ctypes.c_int32),
-                ("adjoint", ctypes.c_int32), ("rho0", ctypes.c_double), ("max_device_bytes", ctypes.c_int64)]
+                ("adjoint", ctypes.c_int32), ("rho0", ctypes.c_double), ("max_device_bytes", ctypes.c_int64),
+                ("scheme", ctypes.c_int32)]
 
 
 class hlb_info_t(ctypes.Structure):
@@ -52,7 +55,7 @@ class hlb_info_t(ctypes.Structure):
                 ("storage", ctypes.c_int32), ("order", ctypes.c_int32), ("bytes_per_lup", ctypes.c_double),
                 ("device_bytes", ctypes.c_int64), ("table_bytes_per_site", ctypes.c_double),
                 ("n_segments", ctypes.c_int64), ("n_iolets", ctypes.c_int64), ("adjoint", ctypes.c_int32),
-                ("porous", ctypes.c_int32)]
+                ("porous", ctypes.c_int32), ("scheme", ctypes.c_int32)]
 
 
 class hlb_stats_t(ctypes.Structure):
@@ -228,7 +231,7 @@ def hlb_info(ctx) -> dict:
     return dict(n_sites=i.n_sites, n_padded=i.n_padded, group_sites=list(i.group_sites)[:5], storage=i.storage,
                 order=i.order, bytes_per_lup=i.bytes_per_lup, device_bytes=i.device_bytes,
                 table_bytes_per_site=i.table_bytes_per_site, n_segments=i.n_segments, n_iolets=i.n_iolets,
-                adjoint=i.adjoint, porous=i.porous)
+                adjoint=i.adjoint, porous=i.porous, scheme=i.scheme)
 
 
 def hlb_macros(ctx, want=("rho", "u", "wss")):
@@ -363,8 +366,10 @@ class Simulation:
 
     @classmethod
     def create(cls, geom, tau: float, storage: str = "f64", order: str = "lex", xcd_remap: int = 8,
-               rho0: float = 1.0, max_device_bytes: int = 0, tables=None, adjoint: bool = False):
+               rho0: float = 1.0, max_device_bytes: int = 0, tables=None, adjoint: bool = False,
+               scheme: str = "pull"):
         opt = hlb_default_options()
+        opt.scheme = SCHEME[scheme]
         opt.storage = STORAGE[storage]
         opt.order = ORDER[order]
         opt.xcd_remap = int(xcd_remap)
