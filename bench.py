@@ -186,6 +186,27 @@ def compare_storages(g, tables, tau, storages, steps):
     return out
 
 
+def run_split(g, tables, tau, storage, steps, warmup, nparts):
+    """The same workload as nparts partitions on this GPU with the halo
+    exchange overlapped (the one-GPU emulation of a domain split)."""
+    import torch
+    from paper_2202_11770_amd import halo
+    t0 = time.time()
+    sp = halo.SplitSimulation(g, tau, storage=storage, tables=tables, nparts=nparts)
+    log(f"split {storage}: {nparts} parts created in {time.time() - t0:.1f}s")
+    sp.step(warmup)
+    sp.synchronize()
+    t0 = time.perf_counter()
+    sp.step(steps)
+    sp.synchronize()
+    dt = time.perf_counter() - t0
+    n_halo = sum(int(b.numel()) for b in sp.send)
+    ghosts = sum(P.glob.size - P.n_owned for P in sp.parts)
+    sp.close()
+    return {"parts": nparts, "mlups": round(g.n * steps / dt / 1e6, 1), "ms_per_step": round(dt / steps * 1e3, 4),
+            "halo_values_per_step": n_halo, "ghost_sites": int(ghosts)}
+
+
 def copy_ceiling(nbytes=4 << 30, reps=20):
     """A plain HIP device-to-device copy (in libhlb): the practical HBM ceiling."""
     from paper_2202_11770_amd import hlb
@@ -220,6 +241,8 @@ def main():
     ap.add_argument("--no-copy", action="store_true")
     ap.add_argument("--schemes", default="pull",
                     help="update orders to time: pull (the headline), and push for the A/B")
+    ap.add_argument("--split", type=int, default=0,
+                    help="also time the workload as this many partitions with the halo exchange (one GPU)")
     ap.add_argument("--compare-steps", type=int, default=0,
                     help="also run every storage for this many steps from rest and report the "
                          "FP32/FP16 errors against the FP64 GPU run")
@@ -265,6 +288,12 @@ def main():
     if not args.no_cpu_baseline and args.workload == "tree20m":
         cpu = cpu_baseline(g, tables, tau)
         log(f"cpu baseline: {cpu}")
+    split = {}
+    if args.split > 1:
+        for st in args.storages.split(","):
+            split[st] = run_split(g, tables, tau, st, args.steps, args.warmup, args.split)
+            split[st]["overhead_vs_single"] = round(results[st]["mlups"] / split[st]["mlups"] - 1.0, 4)
+            log(f"split {st}: {split[st]}")
     compare = None
     if args.compare_steps > 0:
         compare = compare_storages(g, tables, tau, args.storages.split(","), args.compare_steps)
@@ -302,6 +331,8 @@ def main():
         out["errors_vs_f64_gpu"] = {"steps": args.compare_steps, **compare}
     if ab:
         out["schemes"] = ab
+    if split:
+        out["split"] = split
     print(json.dumps(out), flush=True)
 
 

@@ -215,7 +215,7 @@ typedef struct {
   int64_t n_padded;         /* positions incl. padding: each group starts on a multiple of
                                256, the total is a multiple of 4096 (one storage tile) */
   int64_t group_sites[6];   /* sites per group: bulk+wall, inlet, outlet,
-                               inlet+wall, outlet+wall, (unused) */
+                               inlet+wall, outlet+wall, ghosts (partition) */
   int32_t storage;          /* hlb_storage */
   int32_t order;            /* hlb_order */
   double bytes_per_lup;     /* algorithmic HBM bytes per lattice-site update: 19
@@ -241,6 +241,56 @@ typedef struct {
   double step_ms;    /* mean stream time per step, first to last timed event */
 } hlb_stats_t;
 hlb_status hlb_stats(hlb_ctx *ctx, hlb_stats_t *stats);
+
+/* ---- Domain split (Sec. 3.1's edge / mid-domain split with the halo
+ * exchange of Sec. 3.2.3; pull order): one context per partition, the
+ * exchange between them left to the caller (a device copy between two
+ * contexts on one GPU, or RCCL send/recv between GPUs). ----
+ *
+ * hlb_create_part: as hlb_create, with a role per site:
+ *   HLB_PART_MID   an owned site no other partition reads;
+ *   HLB_PART_EDGE  an owned site whose populations another partition reads;
+ *   HLB_PART_GHOST a copy of another partition's site that owned sites pull
+ *                  from: only nbr[x][0] == x and its coordinates are used
+ *                  (its links and type are ignored); it is never updated,
+ *                  and macros, mass and state export skip it (its entries
+ *                  of caller-order outputs are unspecified).
+ * Owned sites' links may point at ghosts (no symmetry required there).  The
+ * edge sites lead the bulk+wall group so that they can be updated first.
+ * Needs the pull scheme and no adjoint.  Ghosts start as zero: exchange once
+ * (hlb_halo_pack, transfer, hlb_halo_unpack) after init or set_state. */
+enum { HLB_PART_MID = 0, HLB_PART_EDGE = 1, HLB_PART_GHOST = 2 };
+hlb_status hlb_create_part(int64_t n_sites, const int32_t *coords, const uint8_t *site_type, const int32_t *nbr,
+                           double tau, const hlb_iolet *iolets, int32_t n_iolets, const hlb_options *opt,
+                           const uint8_t *role, hlb_ctx **out);
+
+/* The halo lists (host, caller ids and directions 0..18): send entry k is
+ * population send_dir[k] of edge site send_site[k]; receive entry k is
+ * population recv_dir[k] of ghost site recv_site[k].  The peer's send list
+ * must list the same (site, direction) pairs in the same order as this
+ * receive list.  send_buf / recv_buf: the caller's device buffers of at
+ * least n_send / n_recv values of the storage type, used by every later
+ * pack and unpack (they must stay valid).  Errors: HLB_EINVAL (a send site
+ * not EDGE, a receive site not GHOST, direction out of range, a missing
+ * buffer), HLB_ESTATE (not a partition). */
+hlb_status hlb_halo_set(hlb_ctx *ctx, int64_t n_send, const int32_t *send_site, const int32_t *send_dir,
+                        void *send_buf, int64_t n_recv, const int32_t *recv_site, const int32_t *recv_dir,
+                        void *recv_buf);
+/* Pack the current state's send values into the send buffer / write the
+ * receive buffer into the current state's ghost slots (context stream). */
+hlb_status hlb_halo_pack(hlb_ctx *ctx);
+hlb_status hlb_halo_unpack(hlb_ctx *ctx);
+/* One step t -> t+1 in two launches, so that the transfer of the edge
+ * values overlaps the rest of the update:
+ *   hlb_step_edge: the iolet groups and the edge blocks of the bulk+wall
+ *     group, then the pack of the new edge values into the send buffer;
+ *   hlb_step_mid: the remaining blocks; then t advances.
+ * The caller moves the peer's send buffer into this receive buffer once the
+ * peer's hlb_step_edge has run (an event on the peer's stream), and calls
+ * hlb_halo_unpack after hlb_step_mid, before the next step.  Between the two
+ * calls only the transfer may touch the context (HLB_ESTATE otherwise). */
+hlb_status hlb_step_edge(hlb_ctx *ctx);
+hlb_status hlb_step_mid(hlb_ctx *ctx);
 
 /* Objective of hlb_adjoint_run (not a rule of the paper).
  *   HLB_OBJ_WSS (default): the wall shear stress (hlb_macros' definition)

@@ -50,6 +50,10 @@ struct Layout {
   int64_t io_begin = 0;         // first position of the iolet groups
   int64_t nio = 0;              // np - io_begin
   int64_t nseg = 0;             // segments of the bulk+wall group
+  int64_t edge_blocks = 0;      // leading 256-position blocks of the bulk+wall group
+                                // holding its edge sites (split step)
+  int64_t ghost_begin = 0;      // positions [ghost_begin, ghost_begin + n_ghost):
+  int64_t n_ghost = 0;          // copies of a peer partition's sites (no update)
 };
 
 struct DevPtrs {
@@ -83,7 +87,11 @@ struct LaunchCfg {
 // One update t -> t+1: reads buffer `src`, writes buffer 1-src.
 // ev_begin / ev_end (may be null) are recorded around the step kernel.
 hipError_t launch_step(const LaunchCfg &cfg, const Layout &L, const DevPtrs &d, int src, int64_t t,
-                       hipStream_t s, hipEvent_t ev_begin, hipEvent_t ev_end);
+                       hipStream_t s, hipEvent_t e0, hipEvent_t e1, int part = 0);
+// Halo pack (pack = true: buffer `buf` -> io) or unpack (io -> buffer `buf`)
+// of n (position, direction) values.
+hipError_t launch_halo(const LaunchCfg &cfg, const DevPtrs &d, int buf, const int32_t *pos, const int32_t *dir,
+                       int64_t n, void *io, bool pack, hipStream_t s);
 // Both buffers := equilibrium of (rho, u) given per caller id in staging
 // (staging: [n][4] doubles rho, ux, uy, uz) or rest if staging is null.
 hipError_t launch_init_eq(const LaunchCfg &cfg, const Layout &L, const DevPtrs &d,

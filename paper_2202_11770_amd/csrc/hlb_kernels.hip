@@ -32,8 +32,10 @@ using namespace dev;
 // One launch per step covers every group (Sec. 3.2.2's per-type kernels as
 // block-uniform code paths of a single launch): the first nb_io blocks take
 // the iolet groups, so that their longer-latency work starts first and
-// overlaps the bulk blocks; the remaining blocks take the bulk+wall group.
-// Every block, hence every wavefront, runs one group's code path only.
+// overlaps the bulk blocks; the remaining nb_bulk blocks take the bulk+wall
+// group's 256-position blocks blk0, blk0+1, ...  (a split step launches the
+// edge blocks and the rest separately).  Every block, hence every wavefront,
+// runs one group's code path only.
 // Per storage type, measured on the 2e7-site tree: the minimum waves per
 // SIMD the step kernel is compiled for (the rare iolet blocks spill to fit,
 // the bulk path does not), and whether population addresses use 32-bit byte
@@ -48,8 +50,8 @@ constexpr bool kStepNarrow = !std::is_same<T, float>::value;
 template <typename T, bool POROUS, bool NARROW>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kStepWaves<T>, 8))) void k_step(const T *__restrict__ A, T *__restrict__ B, GatherArgs a,
                                                  const int32_t *__restrict__ order, int64_t n0, int64_t nb_io,
-                                                 int64_t nb_bulk, int xcd_chunk, typename Acc<T>::type omega,
-                                                 double *acc) {
+                                                 int64_t blk0, int64_t nb_bulk, int xcd_chunk,
+                                                 typename Acc<T>::type omega, double *acc) {
   using C = typename Acc<T>::type;
   constexpr bool SH = kShifted<T>;
   const int64_t b = blockIdx.x;
@@ -66,7 +68,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kStepWav
     const double s = wave_sum(double(flux));
     if ((threadIdx.x & 63) == 0 && s != 0.0) atomicAdd(acc, s);
   } else {
-    const int64_t blk = block_id(b - nb_io, nb_bulk, xcd_chunk);
+    const int64_t blk = blk0 + block_id(b - nb_io, nb_bulk, xcd_chunk);
     const int64_t p = blk * kBlock + threadIdx.x;
     if (p < n0) {
       C g[Q];
@@ -89,7 +91,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kStepWav
 template <typename T, bool POROUS, bool NARROW>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kStepWaves<T>, 8))) void k_step_push(
     const T *__restrict__ A, T *__restrict__ B, GatherArgs a, const int32_t *__restrict__ order, int64_t n0,
-    int64_t nb_io, int64_t nb_bulk, int xcd_chunk, typename Acc<T>::type omega, double *acc) {
+    int64_t nb_io, int64_t blk0, int64_t nb_bulk, int xcd_chunk, typename Acc<T>::type omega, double *acc) {
   using C = typename Acc<T>::type;
   constexpr bool SH = kShifted<T>;
   const int64_t b = blockIdx.x;
@@ -108,7 +110,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kStepWav
     const double s = wave_sum(double(flux));
     if ((threadIdx.x & 63) == 0 && s != 0.0) atomicAdd(acc, s);
   } else {
-    const int64_t blk = block_id(b - nb_io, nb_bulk, xcd_chunk);
+    const int64_t blk = blk0 + block_id(b - nb_io, nb_bulk, xcd_chunk);
     const int64_t p = blk * kBlock + threadIdx.x;
     if (p < n0) {
       C f[Q];
@@ -312,14 +314,19 @@ inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBl
 
 template <typename T>
 hipError_t step_impl(const LaunchCfg &cfg, const Layout &L, const DevPtrs &d, int src, int64_t t,
-                     hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+                     hipStream_t s, hipEvent_t e0, hipEvent_t e1, int part) {
   using C = typename Acc<T>::type;
   const T *A = static_cast<const T *>(d.f[src]);
   T *B = static_cast<T *>(d.f[1 - src]);
   const GatherArgs a = make_args(cfg, L, d, t);
   const C omega = C(1.0 / cfg.tau);
   const int64_t n0 = L.gcnt[0];
-  const int64_t nb_io = (L.nio + kBlock - 1) / kBlock, nb_bulk = (n0 + kBlock - 1) / kBlock;
+  const int64_t nb_all = (n0 + kBlock - 1) / kBlock;
+  // part 0: the whole step; 1: iolet groups + the edge blocks of the
+  // bulk+wall group; 2: its remaining blocks
+  const int64_t nb_io = part == 2 ? 0 : (L.nio + kBlock - 1) / kBlock;
+  const int64_t blk0 = part == 2 ? L.edge_blocks : 0;
+  const int64_t nb_bulk = part == 0 ? nb_all : (part == 1 ? L.edge_blocks : nb_all - L.edge_blocks);
   const unsigned grid = (unsigned)(nb_io + nb_bulk);
   hipError_t er;
   if (e0 && (er = hipEventRecord(e0, s)) != hipSuccess) return er;
@@ -329,11 +336,11 @@ hipError_t step_impl(const LaunchCfg &cfg, const Layout &L, const DevPtrs &d, in
 #define HLB_STEP(P, N)                                                                                    \
   do {                                                                                                  \
     if (cfg.scheme == HLB_SCHEME_PUSH)                                                                  \
-      k_step_push<T, P, N><<<grid, kBlock, 0, s>>>(A, B, a, d.order, n0, nb_io, nb_bulk, cfg.xcd_chunk, \
-                                                   omega, d.acc);                                       \
+      k_step_push<T, P, N><<<grid, kBlock, 0, s>>>(A, B, a, d.order, n0, nb_io, blk0, nb_bulk,          \
+                                                   cfg.xcd_chunk, omega, d.acc);                        \
     else                                                                                                \
-      k_step<T, P, N><<<grid, kBlock, 0, s>>>(A, B, a, d.order, n0, nb_io, nb_bulk, cfg.xcd_chunk, omega, \
-                                              d.acc);                                                   \
+      k_step<T, P, N><<<grid, kBlock, 0, s>>>(A, B, a, d.order, n0, nb_io, blk0, nb_bulk, cfg.xcd_chunk, \
+                                              omega, d.acc);                                            \
   } while (0)
     if (cfg.porous) {
       if (narrow) HLB_STEP(true, kStepNarrow<T>);
@@ -347,6 +354,37 @@ hipError_t step_impl(const LaunchCfg &cfg, const Layout &L, const DevPtrs &d, in
   if ((er = hipGetLastError()) != hipSuccess) return er;
   if (e1 && (er = hipEventRecord(e1, s)) != hipSuccess) return er;
   return hipSuccess;
+}
+
+// Halo exchange (one-GPU emulation of the domain split; the same kernels
+// serve a multi-GPU run): pack copies the listed (position, direction)
+// values of a population buffer into a contiguous buffer, unpack writes a
+// contiguous buffer into the listed slots.  Raw stored values, no rounding.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_pack(const T *__restrict__ A, const int32_t *__restrict__ pos,
+                                                 const int32_t *__restrict__ dir, int64_t n, T *__restrict__ out) {
+  const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (k < n) out[k] = A[pidx(pos[k], dir[k])];
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_unpack(T *__restrict__ A, const int32_t *__restrict__ pos,
+                                                   const int32_t *__restrict__ dir, int64_t n,
+                                                   const T *__restrict__ in) {
+  const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (k < n) A[pidx(pos[k], dir[k])] = in[k];
+}
+
+template <typename T>
+hipError_t halo_impl(const DevPtrs &d, int buf, const int32_t *pos, const int32_t *dir, int64_t n, void *io,
+                     bool pack, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  if (pack)
+    k_pack<T><<<blocks_for(n), kBlock, 0, s>>>(static_cast<const T *>(d.f[buf]), pos, dir, n, static_cast<T *>(io));
+  else
+    k_unpack<T><<<blocks_for(n), kBlock, 0, s>>>(static_cast<T *>(d.f[buf]), pos, dir, n,
+                                                 static_cast<const T *>(io));
+  return hipGetLastError();
 }
 
 template <typename T>
@@ -401,8 +439,13 @@ hipError_t mass_impl(const Layout &L, const DevPtrs &d, int src, hipStream_t s) 
   }
 
 hipError_t launch_step(const LaunchCfg &cfg, const Layout &L, const DevPtrs &d, int src, int64_t t,
-                       hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-  HLB_DISPATCH(cfg.storage, step_impl<T>(cfg, L, d, src, t, s, e0, e1));
+                       hipStream_t s, hipEvent_t e0, hipEvent_t e1, int part) {
+  HLB_DISPATCH(cfg.storage, step_impl<T>(cfg, L, d, src, t, s, e0, e1, part));
+}
+
+hipError_t launch_halo(const LaunchCfg &cfg, const DevPtrs &d, int buf, const int32_t *pos, const int32_t *dir,
+                       int64_t n, void *io, bool pack, hipStream_t s) {
+  HLB_DISPATCH(cfg.storage, halo_impl<T>(d, buf, pos, dir, n, io, pack, s));
 }
 
 hipError_t launch_init_eq(const LaunchCfg &cfg, const Layout &L, const DevPtrs &d, const double *staging,

@@ -127,6 +127,17 @@ struct hlb_ctx {
   hipStream_t stream = nullptr;
   int cur = 0;          // buffer holding the post-collision state of time t
   bool direct = true;   // other buffer holds the pre-collision state of t
+  // partition (hlb_create_part): per-site role and caller id -> position
+  std::vector<uint8_t> role_host;
+  std::vector<int32_t> inv_host;
+  struct Halo {
+    int32_t *send_pos = nullptr, *send_dir = nullptr, *recv_pos = nullptr, *recv_dir = nullptr;
+    void *send_buf = nullptr, *recv_buf = nullptr;  // caller's device buffers
+    int64_t n_send = 0, n_recv = 0;
+    bool defined = false;
+    int64_t bytes = 0;
+  } halo;
+  bool split_pending = false;  // hlb_step_edge done, hlb_step_mid due
   int64_t t = 0;
   int64_t t0 = 0;       // last (re)initialisation
   double m0 = 0.0;      // mass at t0
@@ -179,7 +190,15 @@ hlb_status dev_alloc(hlb_ctx *c, void **p, size_t bytes) {
   return HLB_OK;
 }
 
+void free_halo(hlb_ctx *c) {
+  auto F = [](void *p) { if (p) (void)hipFree(p); };
+  F(c->halo.send_pos); F(c->halo.send_dir); F(c->halo.recv_pos); F(c->halo.recv_dir);
+  c->dev_bytes -= c->halo.bytes;
+  c->halo = hlb_ctx::Halo();
+}
+
 void free_all(hlb_ctx *c) {
+  free_halo(c);
   auto F = [](void *p) { if (p) (void)hipFree(p); };
   F(c->d.f[0]); F(c->d.f[1]); F(c->d.nbr_io); F(c->d.seg_off); F(c->d.seg_base); F(c->d.seg_delta); F(c->d.order); F(c->d.corr); F(c->d.io); F(c->d.tables);
   F(c->d.phi); F(c->d.acc); F(c->d.partial); F(c->d.io_scratch);
@@ -231,7 +250,8 @@ hlb_status upload_tables(hlb_ctx *c) {
 // Mass of the stored zero: N rho0 for the shifted forms (sum_i w_i = 1),
 // 0 for FP64, which stores f itself.
 double mass_offset(const hlb_ctx *c) {
-  return c->cfg.storage == HLB_F64 ? 0.0 : (double)c->L.n_sites * c->cfg.rho0;
+  // the shift sums to rho0 per owned site (ghosts hold no mass of their own)
+  return c->cfg.storage == HLB_F64 ? 0.0 : (double)(c->L.n_sites - c->L.n_ghost) * c->cfg.rho0;
 }
 
 hlb_status check_ctx(const hlb_ctx *c) {
@@ -296,8 +316,9 @@ hlb_status hlb_default_options(hlb_options *opt) {
   return HLB_OK;
 }
 
-hlb_status hlb_create(int64_t n, const int32_t *coords, const uint8_t *type, const int32_t *nbr, double tau,
-                      const hlb_iolet *iolets, int32_t n_iolets, const hlb_options *opt_in, hlb_ctx **out) {
+static hlb_status create_impl(int64_t n, const int32_t *coords, const uint8_t *type, const int32_t *nbr, double tau,
+                              const hlb_iolet *iolets, int32_t n_iolets, const hlb_options *opt_in, const uint8_t *role,
+                              hlb_ctx **out) {
   g_err.clear();
   if (!out) return fail(HLB_EINVAL, "out is null");
   *out = nullptr;
@@ -319,6 +340,17 @@ hlb_status hlb_create(int64_t n, const int32_t *coords, const uint8_t *type, con
   if (opt.adjoint && opt.storage != HLB_F64) return fail(HLB_EINVAL, "the adjoint needs FP64 storage");
   if (opt.scheme != HLB_SCHEME_PULL && opt.scheme != HLB_SCHEME_PUSH) return fail(HLB_EINVAL, "bad scheme %d", opt.scheme);
   if (opt.adjoint && opt.scheme != HLB_SCHEME_PULL) return fail(HLB_EINVAL, "the adjoint needs the pull scheme");
+  int64_t n_ghost = 0;
+  if (role) {
+    if (opt.adjoint || opt.scheme != HLB_SCHEME_PULL)
+      return fail(HLB_EINVAL, "a partition needs the pull scheme and no adjoint");
+    for (int64_t x = 0; x < n; ++x) {
+      if (role[x] > HLB_PART_GHOST) return fail(HLB_EINVAL, "site %lld: bad role %d", (long long)x, (int)role[x]);
+      n_ghost += role[x] == HLB_PART_GHOST;
+    }
+    if (n_ghost == n) return fail(HLB_EINVAL, "a partition needs at least one owned site");
+  }
+  auto is_ghost = [&](int64_t x) { return role && role[x] == HLB_PART_GHOST; };
   for (int k = 0; k < n_iolets; ++k) {
     const hlb_iolet &I = iolets[k];
     if (I.kind != HLB_IOLET_VELOCITY && I.kind != HLB_IOLET_PRESSURE) return fail(HLB_EINVAL, "iolet %d: bad kind", k);
@@ -340,10 +372,14 @@ hlb_status hlb_create(int64_t n, const int32_t *coords, const uint8_t *type, con
     bool wall = false;
     int roles = 0;
     for (int a = 0; a < 3 && ok; ++a) ok = coords[3 * x + a] >= 0 && coords[3 * x + a] < (1 << 20);
+    if (is_ghost(x)) {
+      if (!ok && x < bad_site) bad_site = x;
+      continue;  // a ghost's links and type are not used
+    }
     for (int i = 1; i < Q && ok; ++i) {
       const int32_t y = row[i];
       if (y >= 0) {
-        ok = y < n && nbr[Q * (int64_t)y + OPP(i)] == x;
+        ok = y < n && (is_ghost(y) || nbr[Q * (int64_t)y + OPP(i)] == x);
       } else if (y == HLB_LINK_WALL) {
         wall = true;
       } else {
@@ -373,7 +409,8 @@ hlb_status hlb_create(int64_t n, const int32_t *coords, const uint8_t *type, con
     for (int i = 1; i < Q; ++i) {
       const int32_t y = row[i];
       if (y >= n) return fail(HLB_EINVAL, "site %lld link %d: neighbour id %d out of range", (long long)x, i, y);
-      if (y >= 0 && nbr[Q * (int64_t)y + OPP(i)] != x)
+      if (is_ghost(x)) break;
+      if (y >= 0 && !is_ghost(y) && nbr[Q * (int64_t)y + OPP(i)] != x)
         return fail(HLB_EINVAL, "site %lld link %d: neighbour table not symmetric", (long long)x, i);
       if (y < HLB_LINK_WALL && -(y + 2) >= n_iolets)
         return fail(HLB_EINVAL, "site %lld link %d: iolet id %d out of range", (long long)x, i, -(y + 2));
@@ -402,19 +439,32 @@ hlb_status hlb_create(int64_t n, const int32_t *coords, const uint8_t *type, con
   std::vector<std::vector<KeyId>> grp(kGroups);
   {
     std::vector<int64_t> cnt(kGroups, 0);
-    for (int64_t x = 0; x < n; ++x) cnt[group_of(type[x])]++;
+    for (int64_t x = 0; x < n; ++x)
+      if (!is_ghost(x)) cnt[group_of(type[x])]++;
     for (int g = 0; g < kGroups; ++g) grp[g].resize(cnt[g]);
     std::vector<int64_t> fill(kGroups, 0);
     for (int64_t x = 0; x < n; ++x) {
+      if (is_ghost(x)) continue;
       const int g = group_of(type[x]);
       grp[g][fill[g]++] = KeyId(0, (int32_t)x);
     }
     for (int g = 0; g < kGroups; ++g) {
       auto &v = grp[g];
 #pragma omp parallel for schedule(static)
-      for (int64_t k = 0; k < (int64_t)v.size(); ++k) v[k].first = sfc_key(opt.order, v[k].second, coords + 3 * (int64_t)v[k].second);
+      for (int64_t k = 0; k < (int64_t)v.size(); ++k) {
+        const int32_t x = v[k].second;
+        uint64_t key = sfc_key(opt.order, x, coords + 3 * (int64_t)x);
+        // a partition's edge sites lead the bulk+wall group (bit 63 is
+        // unused by every order's key)
+        if (g == 0 && role && role[x] != HLB_PART_EDGE) key |= uint64_t(1) << 63;
+        v[k].first = key;
+      }
       psort(v);
     }
+    int64_t n_edge0 = 0;
+    if (role)
+      for (const KeyId &kv : grp[0]) n_edge0 += role[kv.second] == HLB_PART_EDGE;
+    L.edge_blocks = (n_edge0 + kSegBlock - 1) / kSegBlock;
   }
   int64_t pos = 0;
   for (int g = 0; g < kGroups; ++g) {
@@ -424,6 +474,10 @@ hlb_status hlb_create(int64_t n, const int32_t *coords, const uint8_t *type, con
     pos = (pos + kGroupAlign - 1) / kGroupAlign * kGroupAlign;
   }
   L.gbeg[kGroups] = pos;
+  // ghost positions follow the groups, in caller order
+  L.ghost_begin = pos;
+  L.n_ghost = n_ghost;
+  pos += n_ghost;
   L.np = (std::max<int64_t>(pos, 1) + kPopTile - 1) / kPopTile * kPopTile;
   L.io_begin = L.gbeg[1];
   L.nio = L.np - L.io_begin;
@@ -436,6 +490,17 @@ hlb_status hlb_create(int64_t n, const int32_t *coords, const uint8_t *type, con
       c->order_host[L.gbeg[g] + k] = x;
       inv[x] = (int32_t)(L.gbeg[g] + k);
     }
+  // ghosts: positions for the pull tables, no caller id (order -1), so that
+  // no kernel updates them and macros, mass and state export skip them
+  {
+    int64_t k = 0;
+    for (int64_t x = 0; x < n; ++x)
+      if (is_ghost(x)) inv[x] = (int32_t)(L.ghost_begin + k++);
+  }
+  if (role) {
+    c->role_host.assign(role, role + n);
+    c->inv_host = inv;
+  }
   grp.clear();
   grp.shrink_to_fit();
 
@@ -659,6 +724,119 @@ hlb_status hlb_set_porosity(hlb_ctx *c, const double *phi) {
   return HLB_OK;
 }
 
+hlb_status hlb_create(int64_t n, const int32_t *coords, const uint8_t *type, const int32_t *nbr, double tau,
+                      const hlb_iolet *iolets, int32_t n_iolets, const hlb_options *opt, hlb_ctx **out) {
+  return create_impl(n, coords, type, nbr, tau, iolets, n_iolets, opt, nullptr, out);
+}
+
+hlb_status hlb_create_part(int64_t n, const int32_t *coords, const uint8_t *type, const int32_t *nbr, double tau,
+                           const hlb_iolet *iolets, int32_t n_iolets, const hlb_options *opt, const uint8_t *role,
+                           hlb_ctx **out) {
+  if (!role) return fail(HLB_EINVAL, "role is null");
+  return create_impl(n, coords, type, nbr, tau, iolets, n_iolets, opt, role, out);
+}
+
+hlb_status hlb_halo_set(hlb_ctx *c, int64_t n_send, const int32_t *send_site, const int32_t *send_dir,
+                        void *send_buf, int64_t n_recv, const int32_t *recv_site, const int32_t *recv_dir,
+                        void *recv_buf) {
+  if (hlb_status st = check_ctx(c)) return st;
+  if (c->role_host.empty()) return fail(HLB_ESTATE, "not a partition (hlb_create_part)");
+  if (n_send < 0 || n_recv < 0 || (n_send > 0 && (!send_site || !send_dir || !send_buf)) ||
+      (n_recv > 0 && (!recv_site || !recv_dir || !recv_buf)))
+    return fail(HLB_EINVAL, "bad halo lists or buffers");
+  const int64_t n = c->L.n_sites;
+  std::vector<int32_t> sp(n_send), sd(n_send), rp(n_recv), rd(n_recv);
+  for (int64_t k = 0; k < n_send; ++k) {
+    const int32_t x = send_site[k], i = send_dir[k];
+    if (x < 0 || x >= n || c->role_host[x] != HLB_PART_EDGE || i < 0 || i >= Q)
+      return fail(HLB_EINVAL, "send entry %lld: needs an edge site and a direction in [0, 19)", (long long)k);
+    sp[k] = c->inv_host[x];
+    sd[k] = i;
+  }
+  for (int64_t k = 0; k < n_recv; ++k) {
+    const int32_t x = recv_site[k], i = recv_dir[k];
+    if (x < 0 || x >= n || c->role_host[x] != HLB_PART_GHOST || i < 0 || i >= Q)
+      return fail(HLB_EINVAL, "receive entry %lld: needs a ghost site and a direction in [0, 19)", (long long)k);
+    rp[k] = c->inv_host[x];
+    rd[k] = i;
+  }
+  if (hlb_status st = bind(c)) return st;
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  free_halo(c);
+  const size_t eb = storage_bytes(c->cfg.storage);
+  void *p = nullptr;
+  auto alloc_cp = [&](void **dst, const void *src, size_t bytes) -> hlb_status {
+    if (hlb_status st = dev_alloc(c, dst, std::max<size_t>(bytes, 16))) return st;
+    c->halo.bytes += (int64_t)std::max<size_t>(bytes, 16);
+    if (src && bytes > 0) {
+      hipError_t e = hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
+      if (e != hipSuccess) return fail(HLB_EDEVICE, "hipMemcpy: %s", hipGetErrorString(e));
+    }
+    return HLB_OK;
+  };
+  hlb_status st;
+  if ((st = alloc_cp(&p, sp.data(), n_send * sizeof(int32_t)))) return st;
+  c->halo.send_pos = static_cast<int32_t *>(p);
+  if ((st = alloc_cp(&p, sd.data(), n_send * sizeof(int32_t)))) return st;
+  c->halo.send_dir = static_cast<int32_t *>(p);
+  if ((st = alloc_cp(&p, rp.data(), n_recv * sizeof(int32_t)))) return st;
+  c->halo.recv_pos = static_cast<int32_t *>(p);
+  if ((st = alloc_cp(&p, rd.data(), n_recv * sizeof(int32_t)))) return st;
+  c->halo.recv_dir = static_cast<int32_t *>(p);
+  (void)eb;
+  c->halo.send_buf = send_buf;
+  c->halo.recv_buf = recv_buf;
+  c->halo.defined = true;
+  c->halo.n_send = n_send;
+  c->halo.n_recv = n_recv;
+  return HLB_OK;
+}
+
+hlb_status hlb_halo_pack(hlb_ctx *c) {
+  if (hlb_status st = check_ctx(c)) return st;
+  if (!c->halo.defined) return fail(HLB_ESTATE, "no halo lists (hlb_halo_set)");
+  if (c->split_pending) return fail(HLB_ESTATE, "a split step is in progress");
+  if (hlb_status st = bind(c)) return st;
+  HIP_TRY(launch_halo(c->cfg, c->d, c->cur, c->halo.send_pos, c->halo.send_dir, c->halo.n_send, c->halo.send_buf,
+                      true, c->stream));
+  return HLB_OK;
+}
+
+hlb_status hlb_halo_unpack(hlb_ctx *c) {
+  if (hlb_status st = check_ctx(c)) return st;
+  if (!c->halo.defined) return fail(HLB_ESTATE, "no halo lists (hlb_halo_set)");
+  if (c->split_pending) return fail(HLB_ESTATE, "a split step is in progress");
+  if (hlb_status st = bind(c)) return st;
+  HIP_TRY(launch_halo(c->cfg, c->d, c->cur, c->halo.recv_pos, c->halo.recv_dir, c->halo.n_recv, c->halo.recv_buf,
+                      false, c->stream));
+  return HLB_OK;
+}
+
+hlb_status hlb_step_edge(hlb_ctx *c) {
+  if (hlb_status st = check_ctx(c)) return st;
+  if (!c->halo.defined) return fail(HLB_ESTATE, "no halo lists (hlb_halo_set)");
+  if (c->split_pending) return fail(HLB_ESTATE, "hlb_step_mid must follow hlb_step_edge");
+  if (hlb_status st = bind(c)) return st;
+  HIP_TRY(launch_step(c->cfg, c->L, c->d, c->cur, c->t, c->stream, nullptr, nullptr, 1));
+  // the edge sites' new post-collision values, from the buffer being written
+  HIP_TRY(launch_halo(c->cfg, c->d, 1 - c->cur, c->halo.send_pos, c->halo.send_dir, c->halo.n_send,
+                      c->halo.send_buf, true, c->stream));
+  c->split_pending = true;
+  return HLB_OK;
+}
+
+hlb_status hlb_step_mid(hlb_ctx *c) {
+  if (hlb_status st = check_ctx(c)) return st;
+  if (!c->split_pending) return fail(HLB_ESTATE, "hlb_step_edge must come first");
+  if (hlb_status st = bind(c)) return st;
+  HIP_TRY(launch_step(c->cfg, c->L, c->d, c->cur, c->t, c->stream, nullptr, nullptr, 2));
+  c->split_pending = false;
+  c->cur = 1 - c->cur;
+  c->direct = false;
+  c->t += 1;
+  return HLB_OK;
+}
+
 hlb_status hlb_set_objective(hlb_ctx *c, int32_t kind, const double *weights) {
   if (hlb_status st = check_ctx(c)) return st;
   if (kind == HLB_OBJ_WSS) {
@@ -727,6 +905,7 @@ static void macro_source(const hlb_ctx *c, int *src, bool *direct) {
 hlb_status hlb_step(hlb_ctx *c, int64_t n) {
   if (hlb_status st = check_ctx(c)) return st;
   if (n < 0) return fail(HLB_EINVAL, "n < 0");
+  if (c->split_pending) return fail(HLB_ESTATE, "a split step is in progress (hlb_step_mid is due)");
   if (hlb_status st = bind(c)) return st;
   for (int64_t s = 0; s < n; ++s) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -777,8 +956,10 @@ hlb_status hlb_macros(hlb_ctx *c, double *rho, double *u, double *wss) {
   if (wss) HIP_TRY(hipMemcpyAsync(wss, dw, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
   if (rho)
-    for (int64_t x = 0; x < n; ++x)
+    for (int64_t x = 0; x < n; ++x) {
+      if (!c->role_host.empty() && c->role_host[x] == HLB_PART_GHOST) continue;  // unspecified
       if (!std::isfinite(rho[x])) return fail(HLB_ENUMERIC, "non-finite density at site %lld", (long long)x);
+    }
   return HLB_OK;
 }
 
@@ -843,6 +1024,7 @@ hlb_status hlb_info(const hlb_ctx *c, hlb_info_t *info) {
   info->n_sites = c->L.n_sites;
   info->n_padded = c->L.np;
   for (int g = 0; g < kGroups; ++g) info->group_sites[g] = c->L.gcnt[g];
+  info->group_sites[kGroups] = c->L.n_ghost;
   info->storage = c->cfg.storage;
   info->order = c->order;
   // 19 loads + 19 stores of the populations, plus the pull tables (read once

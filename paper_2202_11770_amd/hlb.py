@@ -28,6 +28,7 @@ STORAGE = {"f64": HLB_F64, "f32": HLB_F32_SHIFTED, "f16": HLB_F16_SHIFTED}
 HLB_ORDER_INPUT, HLB_ORDER_LEX, HLB_ORDER_MORTON, HLB_ORDER_BRICK = 0, 1, 2, 3
 HLB_IOLET_VELOCITY, HLB_IOLET_PRESSURE = 0, 1
 HLB_SCHEME_PULL, HLB_SCHEME_PUSH = 0, 1
+HLB_LINK_WALL = -1
 SCHEME = {"pull": HLB_SCHEME_PULL, "push": HLB_SCHEME_PUSH}
 ORDER = {"input": 0, "lex": 1, "morton": 2, "brick": 3}
 Q = 19
@@ -96,6 +97,12 @@ _SIGS = {
     "hlb_sync": [_P],
     "hlb_copy_bandwidth": [_i64, _i32, ctypes.POINTER(_d)],
     "hlb_set_objective": [_P, _i32, _P],
+    "hlb_create_part": [_i64, _P, _P, _P, _d, _P, _i32, ctypes.POINTER(hlb_options), _P, _PP],
+    "hlb_halo_set": [_P, _i64, _P, _P, _P, _i64, _P, _P, _P],
+    "hlb_halo_pack": [_P],
+    "hlb_halo_unpack": [_P],
+    "hlb_step_edge": [_P],
+    "hlb_step_mid": [_P],
     "hlb_adjoint_run": [_P, _i64, _i64, _i64, _i32, _P, _P, _P, ctypes.POINTER(_i64)],
     "hlb_last_error": [],
 }
@@ -195,6 +202,53 @@ def hlb_create(coords, site_type, nbr, tau: float, iolets=(), options: hlb_optio
     return out
 
 
+HLB_PART_MID, HLB_PART_EDGE, HLB_PART_GHOST = 0, 1, 2
+
+
+def hlb_create_part(coords, site_type, nbr, tau: float, iolets, role, options: hlb_options | None = None):
+    """hlb_create for one partition of a split domain; role [n] uint8 (HLB_PART_*)."""
+    c, cp = _host(coords, np.int32)
+    t, tp = _host(site_type, np.uint8)
+    nb, nbp = _host(nbr, np.int32)
+    r, rp = _host(role, np.uint8)
+    n = int(t.shape[0])
+    if c.shape != (n, 3) or nb.shape != (n, Q) or r.shape != (n,):
+        raise ValueError("coords must be (n,3), nbr (n,19), role (n,)")
+    io = make_iolets(list(iolets))
+    out = ctypes.c_void_p()
+    opt = ctypes.byref(options) if options is not None else None
+    _check(load().hlb_create_part(n, cp, tp, nbp, float(tau), ctypes.cast(io, _P), len(iolets), opt, rp,
+                                  ctypes.byref(out)), "hlb_create_part")
+    return out
+
+
+def hlb_halo_set(ctx, send_site, send_dir, send_buf, recv_site, recv_dir, recv_buf):
+    """Halo lists (caller ids, directions) and the caller's device buffers
+    (torch tensors or raw device addresses) of the storage type."""
+    ss, ssp = _host(send_site, np.int32)
+    sd, sdp = _host(send_dir, np.int32)
+    rs, rsp = _host(recv_site, np.int32)
+    rd, rdp = _host(recv_dir, np.int32)
+    _check(load().hlb_halo_set(ctx, ss.size, ssp, sdp, _devptr(send_buf), rs.size, rsp, rdp, _devptr(recv_buf)),
+           "hlb_halo_set")
+
+
+def hlb_halo_pack(ctx):
+    _check(load().hlb_halo_pack(ctx), "hlb_halo_pack")
+
+
+def hlb_halo_unpack(ctx):
+    _check(load().hlb_halo_unpack(ctx), "hlb_halo_unpack")
+
+
+def hlb_step_edge(ctx):
+    _check(load().hlb_step_edge(ctx), "hlb_step_edge")
+
+
+def hlb_step_mid(ctx):
+    _check(load().hlb_step_mid(ctx), "hlb_step_mid")
+
+
 def hlb_destroy(ctx):
     _check(load().hlb_destroy(ctx), "hlb_destroy")
 
@@ -228,7 +282,7 @@ def hlb_step(ctx, n: int):
 def hlb_info(ctx) -> dict:
     i = hlb_info_t()
     _check(load().hlb_info(ctx, ctypes.byref(i)), "hlb_info")
-    return dict(n_sites=i.n_sites, n_padded=i.n_padded, group_sites=list(i.group_sites)[:5], storage=i.storage,
+    return dict(n_sites=i.n_sites, n_padded=i.n_padded, group_sites=list(i.group_sites), storage=i.storage,
                 order=i.order, bytes_per_lup=i.bytes_per_lup, device_bytes=i.device_bytes,
                 table_bytes_per_site=i.table_bytes_per_site, n_segments=i.n_segments, n_iolets=i.n_iolets,
                 adjoint=i.adjoint, porous=i.porous, scheme=i.scheme)

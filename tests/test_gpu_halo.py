@@ -1,0 +1,84 @@
+"""One-GPU emulation of the domain split (hlb_create_part, hlb_halo_*,
+hlb_step_edge / hlb_step_mid, paper_2202_11770_amd/halo.py).
+
+Each site's update reads the same values in the same order whether its
+neighbours are owned or ghost copies, so the split run must reproduce the
+single-domain run bit for bit, in every storage.
+"""
+import numpy as np
+import pytest
+
+from paper_2202_11770_amd import geometry as G
+from paper_2202_11770_amd import halo, hlb
+
+pytestmark = pytest.mark.gpu
+
+
+def _tree(seed=3, generations=3, target=30000):
+    g = G.tree(seed=seed, generations=generations, target_sites=target)
+    s = np.arange(200)
+    tables = [0.02 * 0.5 * (1 - np.cos(2 * np.pi * s / 200)) if io.kind == G.VELOCITY else
+              1.0 + 0.001 * np.sin(2 * np.pi * s / 200) for io in g.iolets]
+    return g, tables
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
+@pytest.mark.parametrize("case", ["tree2", "cylinder2", "tree3"])
+def test_split_matches_single_domain_bitwise(case, storage):
+    if case == "cylinder2":
+        g, tables, tau, steps, k = G.cylinder(), None, 0.8, 500, 2
+    elif case == "tree2":
+        (g, tables), tau, steps, k = _tree(), 0.6, 300, 2
+    else:
+        (g, tables), tau, steps, k = _tree(5, 4, 60000), 0.6, 200, 3
+    print(f"case: {case} {g.n} sites, {k} parts, {steps} steps, {storage}", flush=True)
+    sim = hlb.Simulation.create(g, tau, storage=storage, tables=tables)
+    sim.step(steps)
+    rho, u, wss = sim.macros()
+    m, _ = hlb.hlb_mass_balance(sim.ctx)
+    sim.close()
+    sp = halo.SplitSimulation(g, tau, storage=storage, tables=tables, nparts=k)
+    sp.step(steps)
+    sp.synchronize()
+    rho2, u2, wss2 = sp.macros()
+    m2 = sp.mass()
+    sp.close()
+    print(f"max |drho| {np.abs(rho - rho2).max():.1e} max |du| {np.abs(u - u2).max():.1e} "
+          f"mass rel {(m2 - m) / m:.1e}", flush=True)
+    assert np.array_equal(rho, rho2) and np.array_equal(u, u2) and np.array_equal(wss, wss2)
+    assert abs(m2 - m) <= 1e-12 * m
+
+
+def test_split_porous_and_errors():
+    g, tables = _tree()
+    phi = np.zeros(g.n)
+    ws = g.wall_sites()
+    phi[ws] = np.random.default_rng(1).uniform(0, 0.3, ws.size)
+    sim = hlb.Simulation.create(g, 0.6, tables=tables)
+    hlb.hlb_set_porosity(sim.ctx, phi)
+    sim.step(150)
+    ref = sim.macros()
+    sim.close()
+    sp = halo.SplitSimulation(g, 0.6, tables=tables, nparts=2)
+    for P, ctx in zip(sp.parts, sp.ctx):
+        hlb.hlb_set_porosity(ctx, phi[P.glob])
+    sp.step(150)
+    got = sp.macros()
+    for a, b in zip(ref, got):
+        assert np.array_equal(a, b)
+    ctx = sp.ctx[0]
+    P = sp.parts[0]
+    assert hlb.hlb_info(ctx)["group_sites"][5] == P.glob.size - P.n_owned
+    hlb.hlb_step_edge(ctx)
+    with pytest.raises(hlb.HLBError, match="split step"):
+        hlb.hlb_step(ctx, 1)
+    with pytest.raises(hlb.HLBError, match="split step"):
+        hlb.hlb_halo_pack(ctx)
+    hlb.hlb_step_mid(ctx)
+    with pytest.raises(hlb.HLBError, match="hlb_step_edge must come first"):
+        hlb.hlb_step_mid(ctx)
+    mid = np.nonzero(P.role == hlb.HLB_PART_MID)[0][:1].astype(np.int32)
+    with pytest.raises(hlb.HLBError, match="edge site"):
+        hlb.hlb_halo_set(ctx, mid, np.ones(1, np.int32), sp.send[0], np.zeros(0, np.int32),
+                         np.zeros(0, np.int32), sp.recv[0])
+    sp.close()
