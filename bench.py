@@ -103,11 +103,13 @@ def stored_traffic(storage, n_sites):
     return None
 
 
-def run_storage(g, tables, tau, storage, steps, warmup, scheme="pull"):
+def run_storage(g, tables, tau, storage, steps, warmup, scheme="pull", windkessel=None):
     import torch
     from paper_2202_11770_amd import hlb
     t0 = time.time()
     sim = hlb.Simulation.create(g, tau, storage=storage, tables=tables, scheme=scheme)
+    for k, m in (windkessel or {}).items():
+        hlb.hlb_set_windkessel(sim.ctx, k, m)
     info = sim.info()
     log(f"{storage}: context created in {time.time() - t0:.1f}s, {info['device_bytes'] / 2**30:.1f} GiB on the device")
     sim.step(warmup)
@@ -241,6 +243,8 @@ def main():
     ap.add_argument("--no-copy", action="store_true")
     ap.add_argument("--schemes", default="pull",
                     help="update orders to time: pull (the headline), and push for the A/B")
+    ap.add_argument("--windkessel", action="store_true",
+                    help="also time the workload with every pressure outlet a three-element Windkessel")
     ap.add_argument("--split", type=int, default=0,
                     help="also time the workload as this many partitions with the halo exchange (one GPU)")
     ap.add_argument("--compare-steps", type=int, default=0,
@@ -288,6 +292,15 @@ def main():
     if not args.no_cpu_baseline and args.workload == "tree20m":
         cpu = cpu_baseline(g, tables, tau)
         log(f"cpu baseline: {cpu}")
+    wk = {}
+    if args.windkessel:
+        from paper_2202_11770_amd import geometry as G
+        models = {k: (1.0, 0.01, 2000.0, 0.02, 0.0) for k, io in enumerate(g.iolets) if io.kind == G.PRESSURE}
+        for st in args.storages.split(","):
+            r = run_storage(g, tables, tau, st, args.steps, args.warmup, windkessel=models)
+            wk[st] = {"outlets": len(models), "mlups": round(r["mlups"], 1), "ms_per_step": round(r["ms_per_step"], 4),
+                      "overhead_vs_fixed": round(results[st]["mlups"] / r["mlups"] - 1.0, 4)}
+            log(f"windkessel {st}: {wk[st]}")
     split = {}
     if args.split > 1:
         for st in args.storages.split(","):
@@ -333,6 +346,8 @@ def main():
         out["schemes"] = ab
     if split:
         out["split"] = split
+    if wk:
+        out["windkessel"] = wk
     print(json.dumps(out), flush=True)
 
 

@@ -242,6 +242,28 @@ typedef struct {
 } hlb_stats_t;
 hlb_status hlb_stats(hlb_ctx *ctx, hlb_stats_t *stats);
 
+/* Windkessel outlet (not a rule of the paper; its outlook names resistance
+ * and physiological outlets): pressure iolet k takes its ghost density from
+ * a three-element model driven by its outflow Q_k(s) (net mass leaving
+ * through the iolet's links during the update s -> s+1, as in
+ * HLB_OBJ_IOLET_FLUX), in lattice density units:
+ *   rho_k(s+1) = rho_ref + R1 Q_k(s) + X(s+1),
+ *   X(s+1) = X(s) + (Q_k(s) - X(s)/R2) / C   if C > 0 (no leak term if R2 = 0),
+ *   X(s+1) = R2 Q_k(s)                       if C = 0 (resistance R1 + R2).
+ * Each update's outflow is accumulated in FP64 by the step kernel and the
+ * state advanced by one small kernel after it.  rho_k starts at rho_ref + X0.
+ * w = NULL turns the model off (the iolet keeps its last table);
+ * hlb_set_iolet_table on the iolet also turns it off.  R1, C, R2 >= 0 and,
+ * if C > 0 and R2 > 0, R2 C >= 1.  Not with hlb_adjoint_run or a partition.
+ * hlb_windkessel_state: the density the next update uses, X and the last
+ * update's outflow (synchronises).  State files and snapshots do not
+ * include the model's state. */
+typedef struct {
+  double rho_ref, R1, C, R2, X0;
+} hlb_windkessel;
+hlb_status hlb_set_windkessel(hlb_ctx *ctx, int32_t k, const hlb_windkessel *w);
+hlb_status hlb_windkessel_state(hlb_ctx *ctx, int32_t k, double *rho_next, double *X, double *Q_last);
+
 /* ---- Domain split (Sec. 3.1's edge / mid-domain split with the halo
  * exchange of Sec. 3.2.3; pull order): one context per partition, the
  * exchange between them left to the caller (a device copy between two

@@ -188,6 +188,34 @@ class Problem:
             raise ValueError("bad link code")
         return Q[: self.n_io]
 
+    def set_table(self, k: int, values):
+        """Replace iolet k's per-step table."""
+        tab = np.ascontiguousarray(values, dtype=np.float64).reshape(-1)
+        self._tables[k] = tab
+        self.io[k].table = tab.ctypes.data_as(ctypes.c_void_p)
+        self.io[k].table_len = tab.size
+
+    def run_windkessel(self, f, t0: int, nsteps: int, models: dict) -> dict:
+        """nsteps updates from time t0 with Windkessel outlets.  models maps a
+        pressure iolet k to (rho_ref, R1, C, R2, X0): the update s -> s+1
+        uses rho_k(s); its outflow Q_k(s) (iolet_flux) then gives
+          X(s+1) = X(s) + (Q - X/R2)/C  (C > 0; no X/R2 term if R2 = 0),
+                   R2 Q                  (C = 0),
+          rho_k(s+1) = rho_ref + R1 Q + X(s+1).
+        f is advanced in place; returns {k: (rho_next, X, Q_last)}."""
+        st = {k: [m[4], m[0] + m[4], 0.0] for k, m in models.items()}
+        for s in range(nsteps):
+            t = t0 + s
+            for k in models:
+                self.set_table(k, [st[k][1]])
+            Q = self.iolet_flux(f, t)
+            self.run(f, t, 1)
+            for k, (rho_ref, R1, C, R2, _) in models.items():
+                X = st[k][0]
+                X = X + (Q[k] - (X / R2 if R2 > 0 else 0.0)) / C if C > 0 else R2 * Q[k]
+                st[k] = [X, rho_ref + R1 * Q[k] + X, Q[k]]
+        return {k: (v[1], v[0], v[2]) for k, v in st.items()}
+
     def objective(self, f0, t0: int, nsteps: int, obj_t0: int, obj_t1: int, weights=None) -> float:
         """J of adjoint() by a plain forward run (no derivatives)."""
         f = np.array(f0, dtype=np.float64, copy=True)

@@ -262,6 +262,7 @@ hipError_t launch_adjoint_step(const LaunchCfg &cfg, const Layout &L, const DevP
   if (cfg.storage != HLB_F64) return hipErrorInvalidValue;
   AdjArgs A;
   A.a = make_args(cfg, L, d, t - 1);
+  A.a.io_flux = nullptr;
   A.S = static_cast<const double *>(d.f[src]);
   A.mu = b.mu;
   A.nu = b.nu;

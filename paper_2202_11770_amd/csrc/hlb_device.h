@@ -114,6 +114,39 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
+// Per-site outflow of a Windkessel outlet (k < 0: none), gathered while the
+// site's links are processed; a site touching a second such outlet adds that
+// one directly.
+struct WkFlux {
+  int k = -1;
+  double q = 0.0;
+  __device__ void add(double *acc, int kk, double v) {
+    if (k < 0 || k == kk) {
+      k = kk;
+      q += v;
+    } else {
+      atomicAdd(acc + kk, v);
+    }
+  }
+};
+
+// acc[k] += the wavefront's summed q of every outlet k, one atomic per
+// distinct k (the sites of one outlet are mostly neighbours in the iolet
+// groups).  All 64 lanes must call it.
+__device__ inline void wave_add_grouped(double *acc, const WkFlux &w) {
+  bool pending = w.k >= 0;
+  for (;;) {
+    const uint64_t mask = __ballot(pending);
+    if (mask == 0) break;
+    const int leader = __ffsll((unsigned long long)mask) - 1;
+    const int kl = __shfl(w.k, leader, 64);
+    const bool mine = pending && w.k == kl;
+    const double s = wave_sum(mine ? w.q : 0.0);
+    if ((int)(threadIdx.x & 63) == leader) atomicAdd(acc + kl, s);
+    if (mine) pending = false;
+  }
+}
+
 // Moments (eqs. (5), (6)) of stored values s: rho = sum f, j = sum f c.
 // Sums run in ascending i.  For the shifted forms rho = rho0 + sum s.
 template <bool SH, typename C>
@@ -169,6 +202,8 @@ struct GatherArgs {
   const double *corr;
   const IoletDev *io;
   const double *tables;
+  const double *wk_rho;  // Windkessel outlet densities [n_iolets][2] by time parity
+  double *io_flux;       // outflow accumulators of Windkessel outlets, or null (no accumulation)
   int64_t t;           // the update t -> t+1 uses the tables at t
   const double *phi;   // porosity or null
   double rho0;
@@ -207,12 +242,15 @@ __device__ inline void bulk_offsets(const GatherArgs &a, int64_t p, int64_t blk,
 //                                 m = x - c_i/2, U = A_k(t) W(m) v_k
 //   pressure iolet (ghost rho):   f_i = f_i^eq(rho_k(t), (u.n) n),
 //                                 u the site's velocity at time t
-// Returns the mass the boundary rules added (filled - reflected).
+// Returns the mass the boundary rules added (filled - reflected).  With
+// a.io_flux set, the outflow of Windkessel outlets goes to *wkf (which must
+// then be given).
 // IOLET = false: the site has only fluid and wall links.
 // blk: the kSegBlock-position block of p (bulk+wall group only).
 // NARROW: see at().
 template <bool IOLET, bool POROUS, bool SH, bool NARROW = false, typename T, typename C>
-__device__ inline C gather(const T *__restrict__ A, int64_t p, int64_t blk, const GatherArgs &a, C (&g)[Q]) {
+__device__ inline C gather(const T *__restrict__ A, int64_t p, int64_t blk, const GatherArgs &a, C (&g)[Q],
+                           WkFlux *wkf = nullptr) {
   const int64_t np = a.np;
   C flux = 0;
   if constexpr (!IOLET) {
@@ -272,8 +310,9 @@ __device__ inline C gather(const T *__restrict__ A, int64_t p, int64_t blk, cons
         v = back;
         if constexpr (POROUS) v = back - C(a.phi[p]) * (back - rest<SH, C>(i, C(a.rho0)));
       } else {
-        const IoletDev K = a.io[-code - 2];
-        const double val = a.tables[K.tab_off + a.t % K.tab_len];
+        const int k = -code - 2;
+        const IoletDev K = a.io[k];
+        const double val = K.wk ? a.wk_rho[2 * k + (a.t & 1)] : a.tables[K.tab_off + a.t % K.tab_len];
         if (K.kind == HLB_IOLET_VELOCITY) {
           v = back + C(a.corr[(int64_t)(i - 1) * a.nio + (p - a.io_begin)] * val);
         } else {
@@ -282,6 +321,7 @@ __device__ inline C gather(const T *__restrict__ A, int64_t p, int64_t blk, cons
           const C uu = C(1.5) * (gx * gx + gy * gy + gz * gz);
           v = s_eq<SH>(i, C(val - a.rho0), C(val), gx, gy, gz, uu);
         }
+        if (K.wk && a.io_flux) wkf->add(a.io_flux, k, double(back - v));
       }
       flux += v - back;
       g[i] = v;
@@ -301,7 +341,7 @@ __device__ inline C gather(const T *__restrict__ A, int64_t p, int64_t blk, cons
 // added.
 template <bool IOLET, bool POROUS, bool SH, bool NARROW, typename T, typename C>
 __device__ inline C scatter(T *__restrict__ B, int64_t p, int64_t blk, const GatherArgs &a, const C (&fp)[Q], C ux,
-                            C uy, C uz) {
+                            C uy, C uz, WkFlux *wkf = nullptr) {
   const int64_t np = a.np;
   const int32_t p32 = (int32_t)p;
   C flux = 0;
@@ -338,8 +378,9 @@ __device__ inline C scatter(T *__restrict__ B, int64_t p, int64_t blk, const Gat
         v = back;
         if constexpr (POROUS) v = back - C(a.phi[p]) * (back - rest<SH, C>(i, C(a.rho0)));
       } else {
-        const IoletDev K = a.io[-code - 2];
-        const double val = a.tables[K.tab_off + a.t % K.tab_len];
+        const int k = -code - 2;
+        const IoletDev K = a.io[k];
+        const double val = K.wk ? a.wk_rho[2 * k + (a.t & 1)] : a.tables[K.tab_off + a.t % K.tab_len];
         if (K.kind == HLB_IOLET_VELOCITY) {
           v = back + C(a.corr[(int64_t)(i - 1) * a.nio + (p - a.io_begin)] * val);
         } else {
@@ -348,6 +389,7 @@ __device__ inline C scatter(T *__restrict__ B, int64_t p, int64_t blk, const Gat
           const C uu = C(1.5) * (gx * gx + gy * gy + gz * gz);
           v = s_eq<SH>(i, C(val - a.rho0), C(val), gx, gy, gz, uu);
         }
+        if (K.wk && a.io_flux) wkf->add(a.io_flux, k, double(back - v));
       }
       flux += v - back;
       st_cached(at<NARROW>(B, p32, i), v);
@@ -368,6 +410,8 @@ inline GatherArgs make_args(const LaunchCfg &cfg, const Layout &L, const DevPtrs
   a.corr = d.corr;
   a.io = d.io;
   a.tables = d.tables;
+  a.wk_rho = d.wk_rho;
+  a.io_flux = d.io_flux;
   a.t = t;
   a.phi = cfg.porous ? d.phi : nullptr;
   a.rho0 = cfg.rho0;

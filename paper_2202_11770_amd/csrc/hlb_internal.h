@@ -39,7 +39,15 @@ struct IoletDev {
   int32_t tab_len;  // >= 1
   int64_t tab_off;  // offset into the concatenated table array
   double n[3];      // unit normal into the fluid
-  double pad;
+  int32_t wk;       // 1: a Windkessel outlet (density from wk_rho, outflow accumulated)
+  int32_t pad;
+};
+
+// Windkessel outlet state: rho_k(s+1) = rho_ref + R1 Q_k(s) + X(s+1),
+// X(s+1) = X(s) + (Q_k(s) - X(s)/R2)/C (C > 0; no leak if R2 = 0), or
+// R2 Q_k(s) (C = 0); Q_k(s) the outflow of the update s -> s+1.
+struct WkParams {
+  double rho_ref, R1, C, R2, X, Q;
 };
 
 struct Layout {
@@ -72,6 +80,9 @@ struct DevPtrs {
   double *partial = nullptr;        // [partial_len] reduction scratch
   int64_t partial_len = 0;
   double *io_scratch = nullptr;     // [np*19] host-exchange staging (allocated lazily)
+  double *wk_rho = nullptr;         // [n_iolets][2] Windkessel densities by time parity
+  double *io_flux = nullptr;        // [n_iolets] outflow of the current update (Windkessel outlets)
+  WkParams *wk = nullptr;           // [n_iolets]
 };
 
 struct LaunchCfg {
@@ -127,6 +138,10 @@ hipError_t launch_adjoint_step(const LaunchCfg &cfg, const Layout &L, const DevP
                                hipStream_t s);
 // p[0..n) := 0 (a kernel, so that no memset node lands in a captured graph).
 hipError_t launch_zero(double *p, int64_t n, hipStream_t s);
+// After the update t -> t+1: Windkessel outlets take their outflow, advance
+// their state and set the density of the update t+1 -> t+2; the outflow
+// accumulators are cleared (no memset: the launch may be graph-captured).
+hipError_t launch_windkessel(const DevPtrs &d, int n_io, int64_t t, hipStream_t s);
 // Sum of the stored deviations of buffer `src` into d.partial[0] (FP64).
 hipError_t launch_mass(const LaunchCfg &cfg, const Layout &L, const DevPtrs &d, int src,
                        hipStream_t s);

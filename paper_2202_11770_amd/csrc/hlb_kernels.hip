@@ -58,15 +58,17 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kStepWav
   C flux = 0;
   if (b < nb_io) {
     const int64_t p = a.io_begin + b * kBlock + threadIdx.x;
+    WkFlux wkf;
     if (p < a.np && order[p] >= 0) {
       C g[Q];
-      flux = gather<true, POROUS, SH, NARROW>(A, p, 0, a, g);
+      flux = gather<true, POROUS, SH, NARROW>(A, p, 0, a, g, &wkf);
       collide<SH>(g, omega, C(a.rho0));
 #pragma unroll
       for (int i = 0; i < Q; ++i) st(at<NARROW>(B, (int32_t)p, i), g[i]);
     }
     const double s = wave_sum(double(flux));
     if ((threadIdx.x & 63) == 0 && s != 0.0) atomicAdd(acc, s);
+    if (a.io_flux) wave_add_grouped(a.io_flux, wkf);
   } else {
     const int64_t blk = blk0 + block_id(b - nb_io, nb_bulk, xcd_chunk);
     const int64_t p = blk * kBlock + threadIdx.x;
@@ -98,6 +100,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kStepWav
   C flux = 0;
   if (b < nb_io) {
     const int64_t p = a.io_begin + b * kBlock + threadIdx.x;
+    WkFlux wkf;
     if (p < a.np && order[p] >= 0) {
       C f[Q];
 #pragma unroll
@@ -105,10 +108,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kStepWav
       C dr, rho, jx, jy, jz;
       moments<SH>(f, C(a.rho0), dr, rho, jx, jy, jz);
       collide<SH>(f, omega, C(a.rho0));
-      flux = scatter<true, POROUS, SH, NARROW>(B, p, 0, a, f, jx / rho, jy / rho, jz / rho);
+      flux = scatter<true, POROUS, SH, NARROW>(B, p, 0, a, f, jx / rho, jy / rho, jz / rho, &wkf);
     }
     const double s = wave_sum(double(flux));
     if ((threadIdx.x & 63) == 0 && s != 0.0) atomicAdd(acc, s);
+    if (a.io_flux) wave_add_grouped(a.io_flux, wkf);
   } else {
     const int64_t blk = blk0 + block_id(b - nb_io, nb_bulk, xcd_chunk);
     const int64_t p = blk * kBlock + threadIdx.x;
@@ -305,6 +309,23 @@ __global__ __launch_bounds__(kBlock) void k_mass_final(double *partial, int64_t 
   }
 }
 
+// One thread per iolet (see launch_windkessel).
+__global__ void k_windkessel(const IoletDev *io, WkParams *wk, double *wk_rho, double *io_flux, int n_io,
+                             int64_t t) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n_io || !io[k].wk) return;
+  const double Q = io_flux[k];
+  io_flux[k] = 0.0;
+  WkParams P = wk[k];
+  if (P.C > 0.0)
+    P.X += (Q - (P.R2 > 0.0 ? P.X / P.R2 : 0.0)) / P.C;
+  else
+    P.X = P.R2 * Q;
+  P.Q = Q;
+  wk[k] = P;
+  wk_rho[2 * k + ((t + 1) & 1)] = P.rho_ref + P.R1 * Q + P.X;
+}
+
 __global__ void k_zero(double *p, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0.0;
@@ -392,7 +413,8 @@ hipError_t macros_impl(const LaunchCfg &cfg, const Layout &L, const DevPtrs &d, 
                        int64_t t_prev, double *rho, double *u, double *wss, double *f_out,
                        hipStream_t s) {
   const T *A = static_cast<const T *>(d.f[src]);
-  const GatherArgs a = make_args(cfg, L, d, t_prev < 0 ? 0 : t_prev);
+  GatherArgs a = make_args(cfg, L, d, t_prev < 0 ? 0 : t_prev);
+  a.io_flux = nullptr;  // the re-gather does not count towards the outflow
   if (cfg.porous)
     k_macros<T, true><<<blocks_for(L.np), kBlock, 0, s>>>(A, a, d.order, direct ? 1 : 0, cfg.tau, rho, u,
                                                           wss, f_out);
@@ -461,6 +483,12 @@ hipError_t launch_macros(const LaunchCfg &cfg, const Layout &L, const DevPtrs &d
 hipError_t launch_set_state(const LaunchCfg &cfg, const Layout &L, const DevPtrs &d, int pre,
                             const double *staging, hipStream_t s) {
   HLB_DISPATCH(cfg.storage, set_state_impl<T>(cfg, L, d, pre, staging, s));
+}
+
+hipError_t launch_windkessel(const DevPtrs &d, int n_io, int64_t t, hipStream_t s) {
+  if (n_io <= 0 || !d.wk) return hipSuccess;
+  k_windkessel<<<(n_io + 63) / 64, 64, 0, s>>>(d.io, d.wk, d.wk_rho, d.io_flux, n_io, t);
+  return hipGetLastError();
 }
 
 hipError_t launch_zero(double *p, int64_t n, hipStream_t s) {

@@ -138,6 +138,9 @@ struct hlb_ctx {
     int64_t bytes = 0;
   } halo;
   bool split_pending = false;  // hlb_step_edge done, hlb_step_mid due
+  // Windkessel outlets (hlb_set_windkessel)
+  std::vector<int32_t> wk_on;
+  int n_wk = 0;
   int64_t t = 0;
   int64_t t0 = 0;       // last (re)initialisation
   double m0 = 0.0;      // mass at t0
@@ -202,6 +205,7 @@ void free_all(hlb_ctx *c) {
   auto F = [](void *p) { if (p) (void)hipFree(p); };
   F(c->d.f[0]); F(c->d.f[1]); F(c->d.nbr_io); F(c->d.seg_off); F(c->d.seg_base); F(c->d.seg_delta); F(c->d.order); F(c->d.corr); F(c->d.io); F(c->d.tables);
   F(c->d.phi); F(c->d.acc); F(c->d.partial); F(c->d.io_scratch);
+  F(c->d.wk_rho); F(c->d.io_flux); F(c->d.wk);
   for (auto &s : c->snaps) { F(s.f[0]); F(s.f[1]); F(s.acc); }
   c->snaps.clear();
   F(c->adj.mu); F(c->adj.nu); F(c->adj.push); F(c->adj.J); F(c->adj.dA); F(c->adj.dphi); F(c->adj.w);
@@ -226,7 +230,8 @@ hlb_status upload_tables(hlb_ctx *c) {
     io[k].tab_len = (int32_t)c->tables[k].size();
     io[k].tab_off = (int64_t)all.size();
     for (int a = 0; a < 3; ++a) io[k].n[a] = c->iolets[k].normal[a];
-    io[k].pad = 0.0;
+    io[k].wk = k < (int)c->wk_on.size() ? c->wk_on[k] : 0;
+    io[k].pad = 0;
     all.insert(all.end(), c->tables[k].begin(), c->tables[k].end());
   }
   if (c->d.tables) {
@@ -697,7 +702,74 @@ hlb_status hlb_set_iolet_table(hlb_ctx *c, int32_t k, const double *v, int64_t l
       if (!(v[s] > 0.0)) return fail(HLB_EINVAL, "ghost density must be > 0");
   if (hlb_status st = bind(c)) return st;
   c->tables[k].assign(v, v + len);
+  if (k < (int32_t)c->wk_on.size() && c->wk_on[k]) {  // a table replaces the Windkessel
+    c->wk_on[k] = 0;
+    c->n_wk--;
+  }
   return upload_tables(c);
+}
+
+hlb_status hlb_set_windkessel(hlb_ctx *c, int32_t k, const hlb_windkessel *w) {
+  if (hlb_status st = check_ctx(c)) return st;
+  const int K = (int)c->iolets.size();
+  if (k < 0 || k >= K) return fail(HLB_EINVAL, "iolet %d out of range", k);
+  if (c->iolets[k].kind != HLB_IOLET_PRESSURE) return fail(HLB_EINVAL, "iolet %d is not a pressure iolet", k);
+  if (!c->role_host.empty()) return fail(HLB_EINVAL, "Windkessel outlets are not supported on a partition");
+  if (w) {
+    const double v[5] = {w->rho_ref, w->R1, w->C, w->R2, w->X0};
+    for (double x : v)
+      if (!std::isfinite(x)) return fail(HLB_EINVAL, "Windkessel parameters must be finite");
+    if (!(w->R1 >= 0.0 && w->C >= 0.0 && w->R2 >= 0.0)) return fail(HLB_EINVAL, "R1, C, R2 must be >= 0");
+    if (w->C > 0.0 && w->R2 > 0.0 && w->R2 * w->C < 1.0)
+      return fail(HLB_EINVAL, "R2 C must be >= 1 (one explicit step per lattice step)");
+    if (!(w->rho_ref + w->X0 > 0.0)) return fail(HLB_EINVAL, "the initial density rho_ref + X0 must be > 0");
+  }
+  if (hlb_status st = bind(c)) return st;
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  if (!c->d.wk) {
+    void *p = nullptr;
+    if (hlb_status st = dev_alloc(c, &p, (size_t)K * sizeof(WkParams))) return st;
+    c->d.wk = static_cast<WkParams *>(p);
+    if (hlb_status st = dev_alloc(c, &p, (size_t)2 * K * sizeof(double))) return st;
+    c->d.wk_rho = static_cast<double *>(p);
+    if (hlb_status st = dev_alloc(c, &p, (size_t)K * sizeof(double))) return st;
+    c->d.io_flux = static_cast<double *>(p);
+    std::vector<double> z((size_t)2 * K, 0.0);
+    HIP_TRY(hipMemcpy(c->d.wk_rho, z.data(), 2 * K * sizeof(double), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(c->d.io_flux, z.data(), K * sizeof(double), hipMemcpyHostToDevice));
+    c->wk_on.assign(K, 0);
+  }
+  const bool was = c->wk_on[k] != 0;
+  if (w) {
+    const WkParams P{w->rho_ref, w->R1, w->C, w->R2, w->X0, 0.0};
+    const double rho[2] = {w->rho_ref + w->X0, w->rho_ref + w->X0};
+    const double zero = 0.0;
+    HIP_TRY(hipMemcpy(c->d.wk + k, &P, sizeof(P), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(c->d.wk_rho + 2 * k, rho, sizeof(rho), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(c->d.io_flux + k, &zero, sizeof(zero), hipMemcpyHostToDevice));
+    c->wk_on[k] = 1;
+    c->n_wk += was ? 0 : 1;
+  } else {
+    c->wk_on[k] = 0;
+    c->n_wk -= was ? 1 : 0;
+  }
+  return upload_tables(c);
+}
+
+hlb_status hlb_windkessel_state(hlb_ctx *c, int32_t k, double *rho_next, double *X, double *Q_last) {
+  if (hlb_status st = check_ctx(c)) return st;
+  if (k < 0 || k >= (int32_t)c->iolets.size() || k >= (int32_t)c->wk_on.size() || !c->wk_on[k])
+    return fail(HLB_EINVAL, "iolet %d is not a Windkessel outlet", k);
+  if (hlb_status st = bind(c)) return st;
+  WkParams P;
+  double rho = 0.0;
+  HIP_TRY(hipMemcpyAsync(&P, c->d.wk + k, sizeof(P), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipMemcpyAsync(&rho, c->d.wk_rho + 2 * k + (c->t & 1), sizeof(rho), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  if (rho_next) *rho_next = rho;
+  if (X) *X = P.X;
+  if (Q_last) *Q_last = P.Q;
+  return HLB_OK;
 }
 
 hlb_status hlb_set_porosity(hlb_ctx *c, const double *phi) {
@@ -920,6 +992,7 @@ hlb_status hlb_step(hlb_ctx *c, int64_t n) {
       e1 = ts.e[1];
     }
     HIP_TRY(launch_step(c->cfg, c->L, c->d, c->cur, c->t, c->stream, e0, e1));
+    if (c->n_wk > 0) HIP_TRY(launch_windkessel(c->d, (int)c->iolets.size(), c->t, c->stream));
     c->cur = 1 - c->cur;
     c->direct = false;
     c->t += 1;
@@ -1265,6 +1338,7 @@ extern "C" hlb_status hlb_adjoint_run(hlb_ctx *c, int64_t n, int64_t obj_t0, int
                                       double *J, double *dJ_dA, double *dJ_dphi, int64_t *forward_steps) {
   if (hlb_status st = check_ctx(c)) return st;
   if (n < 1 || n_snap < 1 || n_snap > 4096 || !J) return fail(HLB_EINVAL, "need n >= 1, 1 <= n_snap <= 4096, J");
+  if (c->n_wk > 0) return fail(HLB_ESTATE, "the adjoint does not cover Windkessel outlets");
   if (c->cfg.storage != HLB_F64 || !c->adj.push || c->cfg.scheme != HLB_SCHEME_PULL)
     return fail(HLB_ESTATE, "the adjoint needs FP64 storage and opt.adjoint = 1 at creation");
   if (hlb_status st = bind(c)) return st;

@@ -51,6 +51,11 @@ class hlb_options(ctypes.Structure):
                 ("scheme", ctypes.c_int32)]
 
 
+class hlb_windkessel(ctypes.Structure):
+    _fields_ = [("rho_ref", ctypes.c_double), ("R1", ctypes.c_double), ("C", ctypes.c_double),
+                ("R2", ctypes.c_double), ("X0", ctypes.c_double)]
+
+
 class hlb_info_t(ctypes.Structure):
     _fields_ = [("n_sites", ctypes.c_int64), ("n_padded", ctypes.c_int64), ("group_sites", ctypes.c_int64 * 6),
                 ("storage", ctypes.c_int32), ("order", ctypes.c_int32), ("bytes_per_lup", ctypes.c_double),
@@ -97,6 +102,8 @@ _SIGS = {
     "hlb_sync": [_P],
     "hlb_copy_bandwidth": [_i64, _i32, ctypes.POINTER(_d)],
     "hlb_set_objective": [_P, _i32, _P],
+    "hlb_set_windkessel": [_P, _i32, ctypes.POINTER(hlb_windkessel)],
+    "hlb_windkessel_state": [_P, _i32, _P, _P, _P],
     "hlb_create_part": [_i64, _P, _P, _P, _d, _P, _i32, ctypes.POINTER(hlb_options), _P, _PP],
     "hlb_halo_set": [_P, _i64, _P, _P, _P, _i64, _P, _P, _P],
     "hlb_halo_pack": [_P],
@@ -200,6 +207,20 @@ def hlb_create(coords, site_type, nbr, tau: float, iolets=(), options: hlb_optio
     _check(load().hlb_create(n, cp, tp, nbp, float(tau), ctypes.cast(io, _P), len(iolets), opt, ctypes.byref(out)),
            "hlb_create")
     return out
+
+
+def hlb_set_windkessel(ctx, k: int, model=None):
+    """model: (rho_ref, R1, C, R2, X0), or None to turn the model off."""
+    w = None if model is None else ctypes.byref(hlb_windkessel(*[float(v) for v in model]))
+    _check(load().hlb_set_windkessel(ctx, int(k), w), "hlb_set_windkessel")
+
+
+def hlb_windkessel_state(ctx, k: int):
+    """(rho the next update uses, X, outflow of the last update)."""
+    r, x, q = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    _check(load().hlb_windkessel_state(ctx, int(k), ctypes.byref(r), ctypes.byref(x), ctypes.byref(q)),
+           "hlb_windkessel_state")
+    return r.value, x.value, q.value
 
 
 HLB_PART_MID, HLB_PART_EDGE, HLB_PART_GHOST = 0, 1, 2
