@@ -209,6 +209,71 @@ def run_split(g, tables, tau, storage, steps, warmup, nparts):
             "halo_values_per_step": n_halo, "ghost_sites": int(ghosts)}
 
 
+def oracle_rate(g, tables, tau, budget_s):
+    """Oracle MLUPS on a bounded sample: steps (after one untimed) until about
+    budget_s of work.  Returns (mlups, steps)."""
+    import oracle
+    P = oracle.Problem(g, tau, tables=tables)
+    f = P.init()
+    t0 = time.perf_counter()
+    P.run(f, 0, 1)
+    one = time.perf_counter() - t0
+    k = max(1, min(2000, int(budget_s / max(one, 1e-4))))
+    t0 = time.perf_counter()
+    P.run(f, 1, k)
+    dt = time.perf_counter() - t0
+    return g.n * k / dt / 1e6, k
+
+
+def gpu_rate(g, tables, tau, storage, steps):
+    from paper_2202_11770_amd import hlb
+    sim = hlb.Simulation.create(g, tau, storage=storage, tables=tables)
+    sim.step(20)
+    hlb.hlb_sync(sim.ctx)
+    t0 = time.perf_counter()
+    sim.step(steps)
+    hlb.hlb_sync(sim.ctx)
+    dt = time.perf_counter() - t0
+    sim.close()
+    return g.n * steps / dt / 1e6
+
+
+def oracle_table(g20, tables20, budget_s=4.0):
+    """The oracle with all host threads and with one, beside the GPU, on the
+    pipe, the benchmark tree, the error subtree of the 2e8-site tree and the
+    tortuous vessel (the sizes where the oracle is practical)."""
+    import oracle
+    import numpy as np
+    from paper_2202_11770_amd import geometry as G
+    seg = G.tree_segments(2, 8, scale=TREE_SCALE_200M, origin=(0.5, 0.5, -0.5))
+    sub = G.subtree(segments=seg, scale=TREE_SCALE_200M, target_sites=2_000_000)
+    tort = G.tortuous()
+    s = np.arange(3000)
+    tort_tab = [0.01 + 0.001 * np.sin(2 * np.pi * s / 3000) if io.kind == G.VELOCITY else np.array([1.0])
+                for io in tort.iolets]
+    cases = [("pipe (13,312 sites)", G.cylinder(), None, 0.8),
+             (f"tree20m ({g20.n} sites)", g20, tables20, 0.6),
+             (f"error subtree of tree200m ({sub.n} sites)", sub,
+              [inlet_table() if io.kind == G.VELOCITY else np.array([1.0]) for io in sub.iolets], 0.6),
+             (f"tortuous vessel ({tort.n} sites)", tort, tort_tab, 0.8)]
+    nmax = oracle.threads()
+    rows = []
+    for name, g, tabs, tau in cases:
+        row = {"case": name, "n_sites": int(g.n)}
+        for nt in (nmax, 1):
+            oracle.set_threads(nt)
+            mlups, k = oracle_rate(g, tabs, tau, budget_s)
+            row[f"oracle_{nt}t_mlups"] = round(mlups, 3)
+            row[f"oracle_{nt}t_steps"] = k
+        oracle.set_threads(nmax)
+        for st in ("f64", "f32", "f16"):
+            row[f"gpu_{st}_mlups"] = round(gpu_rate(g, tabs, tau, st, 500 if g.n < 1e6 else 200), 1)
+        row["gpu_f64_vs_oracle_1t"] = round(row["gpu_f64_mlups"] / row["oracle_1t_mlups"], 1)
+        log(f"oracle table: {row}")
+        rows.append(row)
+    return {"threads": nmax, "rows": rows}
+
+
 def copy_ceiling(nbytes=4 << 30, reps=20):
     """A plain HIP device-to-device copy (in libhlb): the practical HBM ceiling."""
     from paper_2202_11770_amd import hlb
@@ -243,6 +308,8 @@ def main():
     ap.add_argument("--no-copy", action="store_true")
     ap.add_argument("--schemes", default="pull",
                     help="update orders to time: pull (the headline), and push for the A/B")
+    ap.add_argument("--oracle-table", action="store_true",
+                    help="also time the oracle (all threads and one) beside the GPU on four configurations")
     ap.add_argument("--windkessel", action="store_true",
                     help="also time the workload with every pressure outlet a three-element Windkessel")
     ap.add_argument("--split", type=int, default=0,
@@ -292,6 +359,9 @@ def main():
     if not args.no_cpu_baseline and args.workload == "tree20m":
         cpu = cpu_baseline(g, tables, tau)
         log(f"cpu baseline: {cpu}")
+    otab = None
+    if args.oracle_table:
+        otab = oracle_table(g, tables)
     wk = {}
     if args.windkessel:
         from paper_2202_11770_amd import geometry as G
@@ -348,6 +418,8 @@ def main():
         out["split"] = split
     if wk:
         out["windkessel"] = wk
+    if otab:
+        out["oracle_table"] = otab
     print(json.dumps(out), flush=True)
 
 

@@ -64,6 +64,8 @@ def _load():
     lib.orc_wss_sum.restype = d
     lib.orc_threads.argtypes = []
     lib.orc_threads.restype = ctypes.c_int32
+    lib.orc_set_threads.argtypes = [ctypes.c_int32]
+    lib.orc_set_threads.restype = None
     if hasattr(lib, "orc_adj_run"):
         _declare_adjoint(lib)
     _lib = lib
@@ -238,6 +240,11 @@ class Problem:
 
 def threads() -> int:
     return int(_load().orc_threads())
+
+
+def set_threads(n: int):
+    """Use n OpenMP threads in the oracle from now on."""
+    _load().orc_set_threads(int(n))
 
 
 # -- single-site functions -------------------------------------------------

@@ -322,6 +322,14 @@ int32_t orc_threads(void) {
 #endif
 }
 
+void orc_set_threads(int32_t n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
 double orc_wss_sum(int64_t n, const int32_t *nbr, double tau, const double *f) {
   kahan acc = {0.0, 0.0};
   for (int64_t x = 0; x < n; ++x) kadd(&acc, site_wss(f + ORC_Q * x, nbr + ORC_Q * x, tau));

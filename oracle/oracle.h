@@ -124,6 +124,8 @@ int orc_adj_run(int64_t n, const int32_t *coords, const int32_t *nbr, double tau
 
 /* Number of OpenMP threads the oracle uses. */
 int32_t orc_threads(void);
+/* Use n > 0 OpenMP threads from now on (for timing). */
+void orc_set_threads(int32_t n);
 
 /* Sum of WSS over all sites with a wall link (compensated). */
 double orc_wss_sum(int64_t n, const int32_t *nbr, double tau, const double *f);
