@@ -274,6 +274,33 @@ def oracle_table(g20, tables20, budget_s=4.0):
     return {"threads": nmax, "rows": rows}
 
 
+def run_adjoint(g, tables, tau, n=40, n_snap=10):
+    """hlb_adjoint_run on the workload (FP64, WSS objective over the last
+    half of n steps): the reverse step's kernels timed with HIP events and
+    set against their algorithmic bytes per site:
+      k_adj_collide: gather of s (19 x 8 + the pull table), mu read, nu
+                     written (19 x 8 each), porosity derivative read and
+                     written (16), order (4);
+      k_adj_stream:  order (4), the pull table again (its entry opp(i) names
+                     the site that pulled population i), nu gathered and mu
+                     written (19 x 8 each)."""
+    from paper_2202_11770_amd import hlb
+    sim = hlb.Simulation.create(g, tau, tables=tables, adjoint=True)
+    info = sim.info()
+    hlb.hlb_set_timing(sim.ctx, True)
+    t0 = time.perf_counter()
+    J, _, _, fw = hlb.hlb_adjoint_run(sim.ctx, n, n // 2, n, n_snap)
+    wall = time.perf_counter() - t0
+    st = hlb.hlb_stats(sim.ctx)
+    sim.close()
+    bps = 5 * 19 * 8 + 2 * info["table_bytes_per_site"] + 16 + 4 + 4
+    gbs = bps * info["n_sites"] / (st["adj_ms"] * 1e-3) / 1e9
+    return {"steps": n, "snapshots": n_snap, "forward_steps": fw, "wall_s": round(wall, 3),
+            "reverse_step_ms": round(st["adj_ms"], 4), "bytes_per_site": round(bps, 2),
+            "achieved_gbs": round(gbs, 1), "frac": round(gbs / PEAK_GBS, 4),
+            "reverse_mlups": round(info["n_sites"] / st["adj_ms"] / 1e3, 1), "J": J}
+
+
 def copy_ceiling(nbytes=4 << 30, reps=20):
     """A plain HIP device-to-device copy (in libhlb): the practical HBM ceiling."""
     from paper_2202_11770_amd import hlb
@@ -308,6 +335,8 @@ def main():
     ap.add_argument("--no-copy", action="store_true")
     ap.add_argument("--schemes", default="pull",
                     help="update orders to time: pull (the headline), and push for the A/B")
+    ap.add_argument("--adjoint", action="store_true",
+                    help="also time the adjoint's reverse step on the workload (FP64)")
     ap.add_argument("--oracle-table", action="store_true",
                     help="also time the oracle (all threads and one) beside the GPU on four configurations")
     ap.add_argument("--windkessel", action="store_true",
@@ -359,6 +388,10 @@ def main():
     if not args.no_cpu_baseline and args.workload == "tree20m":
         cpu = cpu_baseline(g, tables, tau)
         log(f"cpu baseline: {cpu}")
+    adj = None
+    if args.adjoint:
+        adj = run_adjoint(g, tables, tau)
+        log(f"adjoint: {adj}")
     otab = None
     if args.oracle_table:
         otab = oracle_table(g, tables)
@@ -420,6 +453,8 @@ def main():
         out["windkessel"] = wk
     if otab:
         out["oracle_table"] = otab
+    if adj:
+        out["adjoint"] = adj
     print(json.dumps(out), flush=True)
 
 

@@ -117,8 +117,9 @@ typedef struct {
   int32_t xcd_remap;   /* K > 0: renumber the bulk kernel's workgroups so that
                           each of the 8 XCDs gets K consecutive tiles of every
                           window of 8K tiles (default 8); 0: plain block order */
-  int32_t adjoint;     /* 1: also build the tables of hlb_adjoint_run (FP64
-                          storage only; 72 more bytes per site); default 0 */
+  int32_t adjoint;     /* 1: enable hlb_adjoint_run (FP64 storage, pull
+                          scheme; its buffers are allocated at the first run);
+                          default 0 */
   double rho0;         /* reference density (default 1.0) */
   int64_t max_device_bytes; /* 0: no limit; otherwise HLB_ENOMEM above it */
   int32_t scheme;      /* HLB_SCHEME_PULL (default) or HLB_SCHEME_PUSH */
@@ -224,21 +225,24 @@ typedef struct {
   double table_bytes_per_site; /* neighbour-table bytes read per site update */
   int64_t n_segments;       /* segments of the bulk+wall group's table */
   int64_t n_iolets;         /* iolets given to hlb_create */
-  int32_t adjoint;          /* adjoint tables built (opt.adjoint) */
+  int32_t adjoint;          /* hlb_adjoint_run enabled (opt.adjoint) */
   int32_t porous;           /* a porosity field is set */
   int32_t scheme;           /* hlb_scheme of the context */
 } hlb_info_t;
 hlb_status hlb_info(const hlb_ctx *ctx, hlb_info_t *info);
 
 /* Kernel timing (HIP events on the context stream around each launch of the
- * step kernel) while enabled; hlb_stats reports the steps timed, the mean
- * duration of the step kernel and the mean stream time per step, in
- * milliseconds.  Enabling or disabling resets the counts. */
+ * step kernel, and around each reverse step of hlb_adjoint_run) while
+ * enabled; hlb_stats reports the steps timed, the mean duration of the step
+ * kernel and the mean stream time per step, and the same for the reverse
+ * steps, in milliseconds.  Enabling or disabling resets the counts. */
 hlb_status hlb_set_timing(hlb_ctx *ctx, int32_t enable);
 typedef struct {
   int64_t steps;     /* steps timed since timing was enabled */
   double kernel_ms;  /* mean duration of one step kernel (all site groups) */
   double step_ms;    /* mean stream time per step, first to last timed event */
+  int64_t adj_steps; /* reverse steps of hlb_adjoint_run timed */
+  double adj_ms;     /* mean duration of one reverse step (both adjoint kernels) */
 } hlb_stats_t;
 hlb_status hlb_stats(hlb_ctx *ctx, hlb_stats_t *stats);
 

@@ -5,12 +5,13 @@
 // time t, g_t = G_t(s_{t-1}) the gathered pre-collision state (tables at
 // t-1) and s_t = C(g_t) the BGK collision (eq. (3a), equilibrium eq. (4)),
 // and the objective J = sum_{t in window} sum_x WSS(g_t(x)):
-//   nu_t      = (dC/dg)^T mu_t + dJ_t/dg_t                 (k_adj_collide)
+//   nu_t      = (dC/dg)^T mu_t + dJ_t/dg_t       (k_adj_collide, k_adj_boundary)
 //   mu_{t-1}  = (dG_t/ds_{t-1})^T nu_t                      (k_adj_stream)
 //   dJ/dA_k(t-1) = sum over Ladd links of nu_t,i corr_i
 //   dJ/dphi_x   += sum over wall links of nu_t,i (rest_i - back_i)
-// where mu_t = dJ/ds_t.  The transpose of the pull gather is again a gather,
-// through the push table (the position of x + c_i), so nothing is scattered.
+// where mu_t = dJ/ds_t.  The transpose of the pull gather is again a gather
+// (the site at x + c_i is the pull entry of direction opp(i)), so nothing is
+// scattered and no further table is needed.
 
 #include "hlb_device.h"
 
@@ -24,7 +25,6 @@ struct AdjArgs {
   const double *S;          // s_{t-1}: post-collision state at t-1 (tiled, as the state)
   double *mu;               // mu_t in, mu_{t-1} out (tiled)
   double *nu;               // nu_t (tiled)
-  const int32_t *push;      // [18][np]: position of x + c_i, or the link code
   const int32_t *order;     // caller id per position (-1: padding)
   double omega, tau;
   int in_window;            // t lies in the objective window
@@ -57,114 +57,166 @@ __device__ inline void eq_transpose(const double (&w)[Q], double rho, double ux,
   }
 }
 
+// Link classes of position p in the pull tables: bit i-1 of `wall` is set
+// when the entry of direction i is a wall link, of `iol` when it is an
+// iolet link (the code is then read again where it is needed).
+__device__ inline void link_masks(const GatherArgs &a, int64_t p, uint32_t &wall, uint32_t &iol) {
+  wall = 0;
+  iol = 0;
+  if (p < a.io_begin) {
+    int32_t off[Q - 1];
+    bulk_offsets(a, p, p / kBlock, off);
+#pragma unroll
+    for (int i = 1; i < Q; ++i)
+      if ((uint32_t)((int32_t)p + off[i - 1]) >= (uint32_t)a.np) wall |= 1u << (i - 1);
+  } else {
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+      const int32_t c = a.nbr_io[(int64_t)(i - 1) * a.nio + (p - a.io_begin)];
+      if (c == HLB_LINK_WALL) wall |= 1u << (i - 1);
+      else if (c < HLB_LINK_WALL) iol |= 1u << (i - 1);
+    }
+  }
+}
+
+// nu_t = (dC/dg)^T mu_t for every site (the objective and parameter terms
+// follow in k_adj_boundary, at the sites that have them).  The gathered
+// state g lives only until its moments are known.
 template <bool POROUS>
 __global__ __launch_bounds__(kBlock) void k_adj_collide(AdjArgs A) {
   const GatherArgs &a = A.a;
   const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  double jsum = 0.0;
-  if (p < a.np && A.order[p] >= 0) {
-    const bool bulk = p < a.io_begin;
+  if (p >= a.np || A.order[p] < 0) return;
+  const int32_t p32 = (int32_t)p;
+  double rho, ux, uy, uz;
+  {
     double g[Q];
-    if (bulk)
+    if (p < a.io_begin)
       gather<false, POROUS, false>(A.S, p, p / kBlock, a, g);
     else
       gather<true, POROUS, false>(A.S, p, 0, a, g);
-    double dr, rho, jx, jy, jz;
+    double dr, jx, jy, jz;
     moments<false>(g, 0.0, dr, rho, jx, jy, jz);
-    const double ux = jx / rho, uy = jy / rho, uz = jz / rho;
-    double m[Q], nu[Q];
+    ux = jx / rho;
+    uy = jy / rho;
+    uz = jz / rho;
+  }
+  double m[Q];
 #pragma unroll
-    for (int i = 0; i < Q; ++i) m[i] = A.mu[pidx((int32_t)p, i)];
-    double ea, ebx, eby, ebz;
-    eq_transpose(m, rho, ux, uy, uz, ea, ebx, eby, ebz);
+  for (int i = 0; i < Q; ++i) m[i] = A.mu[pidx(p32, i)];
+  double ea, ebx, eby, ebz;
+  eq_transpose(m, rho, ux, uy, uz, ea, ebx, eby, ebz);
 #pragma unroll
-    for (int j = 0; j < Q; ++j)
-      nu[j] = (1.0 - A.omega) * m[j] + A.omega * (ea + ebx * (cx(j) - ux) + eby * (cy(j) - uy) + ebz * (cz(j) - uz));
-    // link codes of the site (-1 wall, -(2+k) iolet k, >= 0 fluid) and the
-    // wall-link normal
-    int32_t code[Q - 1];
-    int32_t off[Q - 1];
-    if (bulk) bulk_offsets(a, p, p / kBlock, off);
-    double nx = 0, ny = 0, nz = 0;
-    bool any = false;
+  for (int j = 0; j < Q; ++j)
+    A.nu[pidx(p32, j)] =
+        (1.0 - A.omega) * m[j] + A.omega * (ea + ebx * (cx(j) - ux) + eby * (cy(j) - uy) + ebz * (cz(j) - uz));
+}
+
+// The rest of nu_t and the parameter derivatives of the update t-1 -> t, at
+// the sites with wall or iolet links (list, ascending positions):
+//   WSS objective (in the window): + dWSS(g_t)/dg_t, J += WSS;
+//   porosity: dJ/dphi_x += sum over wall links of nu_i (rest_i - back_i);
+//   iolet table values: dJ/dA_k(t-1) += sum over links of k of (nu_i - w_k)
+//     d(fill_i)/dA_k, and with the iolet-flux objective J += w_k (leaving
+//     population - fill) per link.
+template <bool POROUS>
+__global__ __launch_bounds__(kBlock) void k_adj_boundary(AdjArgs A, const int32_t *__restrict__ list, int64_t n_list) {
+  const GatherArgs &a = A.a;
+  const int64_t k_site = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  double jsum = 0.0;
+  WkFlux dtab;  // this site's table-value derivative (one iolet per site, mostly)
+  if (k_site < n_list) {
+    const int64_t p = list[k_site];
+    const int32_t p32 = (int32_t)p;
+    const bool wss_on = A.objective == HLB_OBJ_WSS && A.in_window;
+    uint32_t wall, iol;
+    link_masks(a, p, wall, iol);
+    double m[Q];
 #pragma unroll
-    for (int i = 1; i < Q; ++i) {
-      if (bulk)
-        code[i - 1] = (uint64_t)(p + (int64_t)off[i - 1]) >= (uint64_t)a.np ? HLB_LINK_WALL : 0;
-      else
-        code[i - 1] = a.nbr_io[(int64_t)(i - 1) * a.nio + (p - a.io_begin)];
-      if (code[i - 1] == HLB_LINK_WALL) {
-        any = true;
-        nx -= cx(i);
-        ny -= cy(i);
-        nz -= cz(i);
+    for (int i = 0; i < Q; ++i) m[i] = A.nu[pidx(p32, i)];
+    if (wss_on && wall) {
+      double rho, ux, uy, uz;
+      double pxx = 0, pyy = 0, pzz = 0, pxy = 0, pxz = 0, pyz = 0;  // non-equilibrium stress of g
+      {
+        double g[Q];
+        if (p < a.io_begin)
+          gather<false, POROUS, false>(A.S, p, p / kBlock, a, g);
+        else
+          gather<true, POROUS, false>(A.S, p, 0, a, g);
+        double dr, jx, jy, jz;
+        moments<false>(g, 0.0, dr, rho, jx, jy, jz);
+        ux = jx / rho;
+        uy = jy / rho;
+        uz = jz / rho;
+        const double usq = 1.5 * (ux * ux + uy * uy + uz * uz);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+          const double d = g[i] - s_eq<false>(i, 0.0, rho, ux, uy, uz, usq);
+          pxx += d * cx(i) * cx(i);
+          pyy += d * cy(i) * cy(i);
+          pzz += d * cz(i) * cz(i);
+          pxy += d * cx(i) * cy(i);
+          pxz += d * cx(i) * cz(i);
+          pyz += d * cy(i) * cz(i);
+        }
+      }
+      double nx = 0, ny = 0, nz = 0;
+#pragma unroll
+      for (int i = 1; i < Q; ++i)
+        if (wall & (1u << (i - 1))) {
+          nx -= cx(i);
+          ny -= cy(i);
+          nz -= cz(i);
+        }
+      const double nn = sqrt(nx * nx + ny * ny + nz * nz);
+      if (nn > 0.0) {
+        nx /= nn;
+        ny /= nn;
+        nz /= nn;
+        const double fac = -(1.0 - 1.0 / (2.0 * A.tau));
+        const double tx = fac * (pxx * nx + pxy * ny + pxz * nz);
+        const double ty = fac * (pxy * nx + pyy * ny + pyz * nz);
+        const double tz = fac * (pxz * nx + pyz * ny + pzz * nz);
+        const double tn = tx * nx + ty * ny + tz * nz;
+        const double sx = tx - tn * nx, sy = ty - tn * ny, sz = tz - tn * nz;
+        const double w = sqrt(sx * sx + sy * sy + sz * sz);
+        jsum = w;
+        if (w > 0.0) {
+          // dWSS/d(g - f^eq)_i = fac (c_i.n)(e.c_i), e = s/|s|; then through f^eq(g)
+          double wd[Q];
+#pragma unroll
+          for (int i = 0; i < Q; ++i)
+            wd[i] = fac * (cx(i) * nx + cy(i) * ny + cz(i) * nz) * (cx(i) * sx + cy(i) * sy + cz(i) * sz) / w;
+          double wa, wbx, wby, wbz;
+          eq_transpose(wd, rho, ux, uy, uz, wa, wbx, wby, wbz);
+#pragma unroll
+          for (int j = 0; j < Q; ++j)
+            m[j] += wd[j] - (wa + wbx * (cx(j) - ux) + wby * (cy(j) - uy) + wbz * (cz(j) - uz));
+        }
       }
     }
-    // objective: wall shear stress of g and its gradient (definition of k_macros)
-    const double nn = sqrt(nx * nx + ny * ny + nz * nz);
-    if (A.objective == HLB_OBJ_WSS && A.in_window && any && nn > 0.0) {
-      nx /= nn;
-      ny /= nn;
-      nz /= nn;
-      const double usq = 1.5 * (ux * ux + uy * uy + uz * uz);
-      double pxx = 0, pyy = 0, pzz = 0, pxy = 0, pxz = 0, pyz = 0;
+    double dphi = 0.0;  // at the current porosity (also where none is set)
 #pragma unroll
-      for (int i = 0; i < Q; ++i) {
-        const double d = g[i] - s_eq<false>(i, 0.0, rho, ux, uy, uz, usq);
-        pxx += d * cx(i) * cx(i);
-        pyy += d * cy(i) * cy(i);
-        pzz += d * cz(i) * cz(i);
-        pxy += d * cx(i) * cy(i);
-        pxz += d * cx(i) * cz(i);
-        pyz += d * cy(i) * cz(i);
+    for (int i = 1; i < Q; ++i)
+      if (wall & (1u << (i - 1))) dphi += m[i] * (wgt<double>(i) * a.rho0 - A.S[pidx(p32, opp(i))]);
+    if (iol) {
+      const bool flux = A.objective == HLB_OBJ_IOLET_FLUX && A.in_window;
+      double ox, oy, oz;  // velocity at t-1 (pressure rule)
+      {
+        double s[Q];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) s[i] = A.S[pidx(p32, i)];
+        double sdr, srho, sjx, sjy, sjz;
+        moments<false>(s, 0.0, sdr, srho, sjx, sjy, sjz);
+        ox = sjx / srho;
+        oy = sjy / srho;
+        oz = sjz / srho;
       }
-      const double fac = -(1.0 - 1.0 / (2.0 * A.tau));
-      const double tx = fac * (pxx * nx + pxy * ny + pxz * nz);
-      const double ty = fac * (pxy * nx + pyy * ny + pyz * nz);
-      const double tz = fac * (pxz * nx + pyz * ny + pzz * nz);
-      const double tn = tx * nx + ty * ny + tz * nz;
-      const double sx = tx - tn * nx, sy = ty - tn * ny, sz = tz - tn * nz;
-      const double w = sqrt(sx * sx + sy * sy + sz * sz);
-      jsum = w;
-      if (w > 0.0) {
-        // dWSS/d(g - f^eq)_i = fac (c_i.n)(e.c_i), e = s/|s|; then through f^eq(g)
-        double wd[Q];
+      double q = 0.0;
 #pragma unroll
-        for (int i = 0; i < Q; ++i)
-          wd[i] = fac * (cx(i) * nx + cy(i) * ny + cz(i) * nz) * (cx(i) * sx + cy(i) * sy + cz(i) * sz) / w;
-        double wa, wbx, wby, wbz;
-        eq_transpose(wd, rho, ux, uy, uz, wa, wbx, wby, wbz);
-#pragma unroll
-        for (int j = 0; j < Q; ++j)
-          nu[j] += wd[j] - (wa + wbx * (cx(j) - ux) + wby * (cy(j) - uy) + wbz * (cz(j) - uz));
-      }
-    }
-    // parameter derivatives from the complete nu_t: porosity at wall links,
-    // the table value (amplitude or ghost density) at iolet links.  With the
-    // iolet-flux objective the update t-1 -> t adds, per iolet link,
-    // w_k (leaving population - filled value) to J, and -w_k times the
-    // filled value's table derivative to that derivative.
-    const bool flux = A.objective == HLB_OBJ_IOLET_FLUX && A.in_window;
-    double ox = 0.0, oy = 0.0, oz = 0.0;  // velocity at t-1 (pressure rule)
-    if (!bulk) {
-      double s[Q];
-#pragma unroll
-      for (int i = 0; i < Q; ++i) s[i] = A.S[pidx((int32_t)p, i)];
-      double sdr, srho, sjx, sjy, sjz;
-      moments<false>(s, 0.0, sdr, srho, sjx, sjy, sjz);
-      ox = sjx / srho;
-      oy = sjy / srho;
-      oz = sjz / srho;
-    }
-    double dphi = 0.0, q = 0.0;
-#pragma unroll
-    for (int i = 1; i < Q; ++i) {
-      const int32_t c = code[i - 1];
-      if (c == HLB_LINK_WALL) {
-        const double back = A.S[pidx((int32_t)p, opp(i))];
-        dphi += nu[i] * (wgt<double>(i) * a.rho0 - back);
-      } else if (c < HLB_LINK_WALL) {
-        const int k = -c - 2;
+      for (int i = 1; i < Q; ++i) {
+        if (!(iol & (1u << (i - 1)))) continue;
+        const int k = -a.nbr_io[(int64_t)(i - 1) * a.nio + (p - a.io_begin)] - 2;
         const IoletDev K = a.io[k];
         const double val = a.tables[K.tab_off + a.t % K.tab_len];
         const double wk = flux ? A.w[k] : 0.0;
@@ -176,44 +228,72 @@ __global__ __launch_bounds__(kBlock) void k_adj_collide(AdjArgs A) {
           const double un = ox * K.n[0] + oy * K.n[1] + oz * K.n[2];
           const double gx = un * K.n[0], gy = un * K.n[1], gz = un * K.n[2];
           coef = s_eq<false>(i, 0.0, 1.0, gx, gy, gz, 1.5 * (gx * gx + gy * gy + gz * gz));
-          out = A.S[pidx((int32_t)p, opp(i))] - val * coef;
+          out = A.S[pidx(p32, opp(i))] - val * coef;
         }
-        atomicAdd(A.dA + (int64_t)k * A.n_steps + A.step, (nu[i] - wk) * coef);
+        dtab.add(A.dA + A.step, k, (m[i] - wk) * coef, A.n_steps);
         q += wk * out;
       }
+      if (flux) jsum = q;
     }
-    if (flux) jsum = q;
     A.dphi[p] += dphi;
+    if (wss_on && wall) {
 #pragma unroll
-    for (int i = 0; i < Q; ++i) A.nu[pidx((int32_t)p, i)] = nu[i];
+      for (int i = 0; i < Q; ++i) A.nu[pidx(p32, i)] = m[i];
+    }
   }
   const double s = wave_sum(jsum);
   if ((threadIdx.x & 63) == 0 && s != 0.0) atomicAdd(A.J, s);
+  wave_add_grouped(A.dA + A.step, dtab, A.n_steps);  // one atomic per iolet per wavefront
 }
 
+// mu_{t-1} = (dG_t/ds_{t-1})^T nu_t (compiled for 4 waves per SIMD, no
+// spills; the default allocation gave 3): population i of p at t-1 went to the
+// site at x + c_i -- the pull entry of direction opp(i), which names the
+// site that pulled it --, was reflected back to p (wall: times 1 - phi;
+// Ladd: plus a constant), or was replaced (pressure iolet: no direct path,
+// but the fill depends on p's velocity at t-1).
 template <bool POROUS>
-__global__ __launch_bounds__(kBlock) void k_adj_stream(AdjArgs A) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_adj_stream(AdjArgs A) {
   const GatherArgs &a = A.a;
   const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (p >= a.np || A.order[p] < 0) return;
+  const int32_t p32 = (int32_t)p;
   const double ph = POROUS ? a.phi[p] : 0.0;
   // iolet-flux objective: a population leaving through a pressure iolet adds
   // w_k to its own adjoint (the fill does not depend on it), and the fill's
   // dependence on u enters with weight (nu - w_k)
+  if (p < a.io_begin) {
+    // bulk+wall group (block-uniform): fluid and wall links only, one load
+    // per link as in the forward gather
+    int32_t off[Q - 1];
+    bulk_offsets(a, p, p / kBlock, off);
+    A.mu[pidx(p32, 0)] = A.nu[pidx(p32, 0)];
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+      const int32_t q = p32 + off[opp(i) - 1];
+      const bool wall = (uint32_t)q >= (uint32_t)a.np;
+      const double v = A.nu[pidx(wall ? p32 : q, wall ? opp(i) : i)];
+      A.mu[pidx(p32, i)] = (POROUS && wall) ? (1.0 - ph) * v : v;
+    }
+    return;
+  }
   const bool flux = A.objective == HLB_OBJ_IOLET_FLUX && A.in_window;
+  // iolet groups: the site's 18 pull entries
+  int32_t code[Q - 1];
+#pragma unroll
+  for (int i = 1; i < Q; ++i) code[i - 1] = a.nbr_io[(int64_t)(i - 1) * a.nio + (p - a.io_begin)];
   double m[Q];
   bool pressure = false;
-  m[0] = A.nu[pidx((int32_t)p, 0)];
+  m[0] = A.nu[pidx(p32, 0)];
 #pragma unroll
   for (int i = 1; i < Q; ++i) {
-    // s_{t-1}[i][p] was read by the site at p + c_i, or reflected back to p
-    const int32_t c = A.push[(int64_t)(i - 1) * a.np + p];
+    const int32_t c = code[opp(i) - 1];
     if (c >= 0) {
-      m[i] = A.nu[pidx((int32_t)c, i)];
+      m[i] = A.nu[pidx(c, i)];
     } else if (c == HLB_LINK_WALL) {
-      m[i] = (1.0 - ph) * A.nu[pidx((int32_t)p, opp(i))];
+      m[i] = (1.0 - ph) * A.nu[pidx(p32, opp(i))];
     } else if (a.io[-c - 2].kind == HLB_IOLET_VELOCITY) {
-      m[i] = A.nu[pidx((int32_t)p, opp(i))];
+      m[i] = A.nu[pidx(p32, opp(i))];
     } else {
       m[i] = flux ? A.w[-c - 2] : 0.0;  // replaced by the ghost-density equilibrium
       pressure = true;
@@ -223,13 +303,13 @@ __global__ __launch_bounds__(kBlock) void k_adj_stream(AdjArgs A) {
     // the ghost equilibrium depends on the site's u at t-1 (moments of s_{t-1})
     double s[Q];
 #pragma unroll
-    for (int i = 0; i < Q; ++i) s[i] = A.S[pidx((int32_t)p, i)];
+    for (int i = 0; i < Q; ++i) s[i] = A.S[pidx(p32, i)];
     double dr, rho, jx, jy, jz;
     moments<false>(s, 0.0, dr, rho, jx, jy, jz);
     const double ux = jx / rho, uy = jy / rho, uz = jz / rho;
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
-      const int32_t c = A.push[(int64_t)(i - 1) * a.np + p];
+      const int32_t c = code[opp(i) - 1];
       if (c >= HLB_LINK_WALL) continue;
       const IoletDev K = a.io[-c - 2];
       if (K.kind != HLB_IOLET_PRESSURE) continue;
@@ -242,14 +322,14 @@ __global__ __launch_bounds__(kBlock) void k_adj_stream(AdjArgs A) {
       const double dy = wgt<double>(o) * rk * (3.0 * cy(o) + 9.0 * cu * cy(o) - 3.0 * gy);
       const double dz = wgt<double>(o) * rk * (3.0 * cz(o) + 9.0 * cu * cz(o) - 3.0 * gz);
       const double wk = flux ? A.w[-c - 2] : 0.0;
-      const double coef = (A.nu[pidx((int32_t)p, o)] - wk) * (dx * K.n[0] + dy * K.n[1] + dz * K.n[2]) / rho;
+      const double coef = (A.nu[pidx(p32, o)] - wk) * (dx * K.n[0] + dy * K.n[1] + dz * K.n[2]) / rho;
 #pragma unroll
       for (int j = 0; j < Q; ++j)
         m[j] += coef * (K.n[0] * (cx(j) - ux) + K.n[1] * (cy(j) - uy) + K.n[2] * (cz(j) - uz));
     }
   }
 #pragma unroll
-  for (int i = 0; i < Q; ++i) A.mu[pidx((int32_t)p, i)] = m[i];
+  for (int i = 0; i < Q; ++i) A.mu[pidx(p32, i)] = m[i];
 }
 
 inline unsigned blocks_of(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
@@ -266,7 +346,6 @@ hipError_t launch_adjoint_step(const LaunchCfg &cfg, const Layout &L, const DevP
   A.S = static_cast<const double *>(d.f[src]);
   A.mu = b.mu;
   A.nu = b.nu;
-  A.push = b.push;
   A.order = d.order;
   A.omega = 1.0 / cfg.tau;
   A.tau = cfg.tau;
@@ -279,11 +358,14 @@ hipError_t launch_adjoint_step(const LaunchCfg &cfg, const Layout &L, const DevP
   A.objective = b.objective;
   A.w = b.w;
   const unsigned grid = blocks_of(L.np);
+  const unsigned grid_b = blocks_of(std::max<int64_t>(b.n_blist, 1));
   if (cfg.porous) {
     k_adj_collide<true><<<grid, kBlock, 0, s>>>(A);
+    if (b.n_blist > 0) k_adj_boundary<true><<<grid_b, kBlock, 0, s>>>(A, b.blist, b.n_blist);
     k_adj_stream<true><<<grid, kBlock, 0, s>>>(A);
   } else {
     k_adj_collide<false><<<grid, kBlock, 0, s>>>(A);
+    if (b.n_blist > 0) k_adj_boundary<false><<<grid_b, kBlock, 0, s>>>(A, b.blist, b.n_blist);
     k_adj_stream<false><<<grid, kBlock, 0, s>>>(A);
   }
   return hipGetLastError();

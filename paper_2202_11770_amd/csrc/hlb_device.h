@@ -120,20 +120,20 @@ __device__ inline double wave_sum(double v) {
 struct WkFlux {
   int k = -1;
   double q = 0.0;
-  __device__ void add(double *acc, int kk, double v) {
+  __device__ void add(double *acc, int kk, double v, int64_t stride = 1) {
     if (k < 0 || k == kk) {
       k = kk;
       q += v;
     } else {
-      atomicAdd(acc + kk, v);
+      atomicAdd(acc + (int64_t)kk * stride, v);
     }
   }
 };
 
-// acc[k] += the wavefront's summed q of every outlet k, one atomic per
-// distinct k (the sites of one outlet are mostly neighbours in the iolet
+// acc[k * stride] += the wavefront's summed q of every outlet k, one atomic
+// per distinct k (the sites of one outlet are mostly neighbours in the iolet
 // groups).  All 64 lanes must call it.
-__device__ inline void wave_add_grouped(double *acc, const WkFlux &w) {
+__device__ inline void wave_add_grouped(double *acc, const WkFlux &w, int64_t stride = 1) {
   bool pending = w.k >= 0;
   for (;;) {
     const uint64_t mask = __ballot(pending);
@@ -142,7 +142,7 @@ __device__ inline void wave_add_grouped(double *acc, const WkFlux &w) {
     const int kl = __shfl(w.k, leader, 64);
     const bool mine = pending && w.k == kl;
     const double s = wave_sum(mine ? w.q : 0.0);
-    if ((int)(threadIdx.x & 63) == leader) atomicAdd(acc + kl, s);
+    if ((int)(threadIdx.x & 63) == leader) atomicAdd(acc + (int64_t)kl * stride, s);
     if (mine) pending = false;
   }
 }

@@ -122,10 +122,11 @@ hipError_t launch_set_state(const LaunchCfg &cfg, const Layout &L, const DevPtrs
 struct AdjBuffers {
   double *mu = nullptr;       // [19][np] adjoint of the post-collision state
   double *nu = nullptr;       // [19][np] adjoint of the pre-collision state
-  int32_t *push = nullptr;    // [18][np] position of x + c_i, or the link code
   double *J = nullptr;        // objective accumulator
   double *dA = nullptr;       // [n_iolets][n_steps]
   double *dphi = nullptr;     // [np] porosity derivative per position
+  int32_t *blist = nullptr;   // positions of the sites with wall or iolet links, ascending
+  int64_t n_blist = 0;
   int32_t objective = HLB_OBJ_WSS;
   double *w = nullptr;        // [n_iolets] iolet-flux weights (device)
 };

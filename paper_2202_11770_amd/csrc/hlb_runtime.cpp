@@ -138,6 +138,7 @@ struct hlb_ctx {
     int64_t bytes = 0;
   } halo;
   bool split_pending = false;  // hlb_step_edge done, hlb_step_mid due
+  bool adj_on = false;         // opt.adjoint at creation
   // Windkessel outlets (hlb_set_windkessel)
   std::vector<int32_t> wk_on;
   int n_wk = 0;
@@ -158,6 +159,10 @@ struct hlb_ctx {
   size_t n_timed = 0;
   int64_t steps_timed = 0;
   double sum_kernel = 0, sum_step = 0;
+  std::vector<TimedStep> adj_pool;  // events around the adjoint step kernels
+  size_t n_adj_timed = 0;
+  int64_t adj_steps_timed = 0;
+  double sum_adj = 0;
   // snapshots
   struct Snap {
     void *f[2] = {nullptr, nullptr};
@@ -208,12 +213,15 @@ void free_all(hlb_ctx *c) {
   F(c->d.wk_rho); F(c->d.io_flux); F(c->d.wk);
   for (auto &s : c->snaps) { F(s.f[0]); F(s.f[1]); F(s.acc); }
   c->snaps.clear();
-  F(c->adj.mu); F(c->adj.nu); F(c->adj.push); F(c->adj.J); F(c->adj.dA); F(c->adj.dphi); F(c->adj.w);
+  F(c->adj.mu); F(c->adj.nu); F(c->adj.J); F(c->adj.dA); F(c->adj.dphi); F(c->adj.w); F(c->adj.blist);
   for (void *q : c->adj_slots) F(q);
   c->adj_slots.clear();
   c->adj = AdjBuffers();
   for (auto &ts : c->pool)
     for (auto &e : ts.e) (void)hipEventDestroy(e);
+  for (auto &ts : c->adj_pool)
+    for (auto &e : ts.e) (void)hipEventDestroy(e);
+  c->adj_pool.clear();
   c->pool.clear();
   if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
   c->d = DevPtrs();
@@ -555,20 +563,18 @@ static hlb_status create_impl(int64_t n, const int32_t *coords, const uint8_t *t
   for (int64_t p = 0; p < n0; ++p) seg_delta[p] = (uint8_t)(segid[p] - segid[(p / kSegBlock) * kSegBlock]);
   segid.clear();
   segid.shrink_to_fit();
-  // ---- adjoint: push table, position of x + c_i or the link code ----
-  std::vector<int32_t> push;
-  if (opt.adjoint) {
-    push.assign((size_t)18 * np, HLB_LINK_WALL);
-#pragma omp parallel for schedule(static)
+  // the adjoint's transposed gather reads the pull tables; it only needs the
+  // list of the sites with wall or iolet links (boundary terms)
+  c->adj_on = opt.adjoint != 0;
+  std::vector<int32_t> blist;
+  if (c->adj_on)
     for (int64_t p = 0; p < np; ++p) {
       const int32_t x = c->order_host[p];
       if (x < 0) continue;
-      for (int i = 1; i < Q; ++i) {
-        const int32_t y = nbr[Q * (int64_t)x + i];
-        push[(size_t)(i - 1) * np + p] = y >= 0 ? inv[y] : y;
-      }
+      bool any = false;
+      for (int i = 1; i < Q && !any; ++i) any = nbr[Q * (int64_t)x + i] < 0;
+      if (any) blist.push_back((int32_t)p);
     }
-  }
   // ---- Ladd coefficients 6 w_i rho0 (c_i . v_k) W_k(x - c_i/2) of velocity-iolet links ----
   std::vector<double> corr((size_t)18 * L.nio, 0.0);
 #pragma omp parallel for schedule(static)
@@ -661,12 +667,13 @@ static hlb_status create_impl(int64_t n, const int32_t *coords, const uint8_t *t
   if ((st = cp(c->d.seg_off, seg_off.data(), seg_off.size() * sizeof(int32_t)))) return bail(st);
   if ((st = cp(c->d.seg_base, seg_base.data(), seg_base.size() * sizeof(int32_t)))) return bail(st);
   if ((st = cp(c->d.seg_delta, seg_delta.data(), seg_delta.size()))) return bail(st);
-  if (!push.empty()) {
-    if ((st = dev_alloc(c, &p, push.size() * sizeof(int32_t)))) return bail(st);
-    c->adj.push = static_cast<int32_t *>(p);
-    if ((st = cp(c->adj.push, push.data(), push.size() * sizeof(int32_t)))) return bail(st);
-  }
   if ((st = cp(c->d.order, c->order_host.data(), np * sizeof(int32_t)))) return bail(st);
+  if (!blist.empty()) {
+    if ((st = dev_alloc(c, &p, blist.size() * sizeof(int32_t)))) return bail(st);
+    c->adj.blist = static_cast<int32_t *>(p);
+    c->adj.n_blist = (int64_t)blist.size();
+    if ((st = cp(c->adj.blist, blist.data(), blist.size() * sizeof(int32_t)))) return bail(st);
+  }
   if (!corr.empty() && (st = cp(c->d.corr, corr.data(), corr.size() * sizeof(double)))) return bail(st);
   if ((st = upload_tables(c))) return bail(st);
   if ((st = hlb_init_equilibrium(c, nullptr, nullptr, 0))) return bail(st);
@@ -1106,7 +1113,7 @@ hlb_status hlb_info(const hlb_ctx *c, hlb_info_t *info) {
   info->bytes_per_lup = 38.0 * (double)storage_bytes(c->cfg.storage) + info->table_bytes_per_site;
   info->n_segments = c->L.nseg;
   info->n_iolets = (int64_t)c->iolets.size();
-  info->adjoint = c->adj.push ? 1 : 0;
+  info->adjoint = c->adj_on ? 1 : 0;
   info->porous = c->cfg.porous ? 1 : 0;
   info->scheme = c->cfg.scheme;
   info->device_bytes = c->dev_bytes;
@@ -1121,6 +1128,9 @@ hlb_status hlb_set_timing(hlb_ctx *c, int32_t enable) {
   c->n_timed = 0;
   c->steps_timed = 0;
   c->sum_kernel = c->sum_step = 0.0;
+  c->n_adj_timed = 0;
+  c->adj_steps_timed = 0;
+  c->sum_adj = 0.0;
   return HLB_OK;
 }
 
@@ -1141,10 +1151,19 @@ hlb_status hlb_stats(hlb_ctx *c, hlb_stats_t *s) {
     c->steps_timed += (int64_t)c->n_timed;
     c->n_timed = 0;
   }
+  for (size_t k = 0; k < c->n_adj_timed; ++k) {
+    float a = 0;
+    HIP_TRY(hipEventElapsedTime(&a, c->adj_pool[k].e[0], c->adj_pool[k].e[1]));
+    c->sum_adj += a;
+  }
+  c->adj_steps_timed += (int64_t)c->n_adj_timed;
+  c->n_adj_timed = 0;
   s->steps = c->steps_timed;
   const double k = c->steps_timed > 0 ? (double)c->steps_timed : 1.0;
   s->kernel_ms = c->sum_kernel / k;
   s->step_ms = c->sum_step / k;
+  s->adj_steps = c->adj_steps_timed;
+  s->adj_ms = c->adj_steps_timed > 0 ? c->sum_adj / (double)c->adj_steps_timed : 0.0;
   return HLB_OK;
 }
 
@@ -1306,7 +1325,20 @@ struct Revolve {
   }
   hlb_status adjoint_step(int64_t t) {  // needs the state of time t-1
     const int in_window = (t > w0 && t <= w1) ? 1 : 0;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (c->timing) {
+      if (c->n_adj_timed == c->adj_pool.size()) {
+        TimedStep ts;
+        for (auto &e : ts.e) HIP_TRY(hipEventCreate(&e));
+        c->adj_pool.push_back(ts);
+      }
+      TimedStep &ts = c->adj_pool[c->n_adj_timed++];
+      e0 = ts.e[0];
+      e1 = ts.e[1];
+      HIP_TRY(hipEventRecord(e0, c->stream));
+    }
     HIP_TRY(launch_adjoint_step(c->cfg, c->L, c->d, c->cur, t, c->adj, in_window, n, t - 1 - t0, c->stream));
+    if (e1) HIP_TRY(hipEventRecord(e1, c->stream));
     return HLB_OK;
   }
   hlb_status reverse(int64_t a, int64_t b, int64_t slot_a, int64_t cfree) {
@@ -1339,7 +1371,7 @@ extern "C" hlb_status hlb_adjoint_run(hlb_ctx *c, int64_t n, int64_t obj_t0, int
   if (hlb_status st = check_ctx(c)) return st;
   if (n < 1 || n_snap < 1 || n_snap > 4096 || !J) return fail(HLB_EINVAL, "need n >= 1, 1 <= n_snap <= 4096, J");
   if (c->n_wk > 0) return fail(HLB_ESTATE, "the adjoint does not cover Windkessel outlets");
-  if (c->cfg.storage != HLB_F64 || !c->adj.push || c->cfg.scheme != HLB_SCHEME_PULL)
+  if (c->cfg.storage != HLB_F64 || !c->adj_on || c->cfg.scheme != HLB_SCHEME_PULL)
     return fail(HLB_ESTATE, "the adjoint needs FP64 storage and opt.adjoint = 1 at creation");
   if (hlb_status st = bind(c)) return st;
   const int64_t np = c->L.np, nio = (int64_t)c->iolets.size();

@@ -65,7 +65,8 @@ class hlb_info_t(ctypes.Structure):
 
 
 class hlb_stats_t(ctypes.Structure):
-    _fields_ = [("steps", ctypes.c_int64), ("kernel_ms", ctypes.c_double), ("step_ms", ctypes.c_double)]
+    _fields_ = [("steps", ctypes.c_int64), ("kernel_ms", ctypes.c_double), ("step_ms", ctypes.c_double),
+                ("adj_steps", ctypes.c_int64), ("adj_ms", ctypes.c_double)]
 
 
 _P = ctypes.c_void_p
@@ -355,7 +356,7 @@ def hlb_set_timing(ctx, enable: bool):
 def hlb_stats(ctx) -> dict:
     s = hlb_stats_t()
     _check(load().hlb_stats(ctx, ctypes.byref(s)), "hlb_stats")
-    return dict(steps=s.steps, kernel_ms=s.kernel_ms, step_ms=s.step_ms)
+    return dict(steps=s.steps, kernel_ms=s.kernel_ms, step_ms=s.step_ms, adj_steps=s.adj_steps, adj_ms=s.adj_ms)
 
 
 def hlb_snapshot_alloc(ctx, n_slots: int):
