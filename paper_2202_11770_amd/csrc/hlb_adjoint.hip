@@ -131,11 +131,10 @@ __global__ __launch_bounds__(kBlock) void k_adj_boundary(AdjArgs A, const int32_
     const bool wss_on = A.objective == HLB_OBJ_WSS && A.in_window;
     uint32_t wall, iol;
     link_masks(a, p, wall, iol);
-    double m[Q];
-#pragma unroll
-    for (int i = 0; i < Q; ++i) m[i] = A.nu[pidx(p32, i)];
+    // WSS of g_t and what its gradient needs (scalars), before nu is loaded
+    double rho = 1.0, ux = 0, uy = 0, uz = 0, nx = 0, ny = 0, nz = 0, sx = 0, sy = 0, sz = 0, w = 0.0;
+    const double fac = -(1.0 - 1.0 / (2.0 * A.tau));
     if (wss_on && wall) {
-      double rho, ux, uy, uz;
       double pxx = 0, pyy = 0, pzz = 0, pxy = 0, pxz = 0, pyz = 0;  // non-equilibrium stress of g
       {
         double g[Q];
@@ -160,7 +159,6 @@ __global__ __launch_bounds__(kBlock) void k_adj_boundary(AdjArgs A, const int32_
           pyz += d * cy(i) * cz(i);
         }
       }
-      double nx = 0, ny = 0, nz = 0;
 #pragma unroll
       for (int i = 1; i < Q; ++i)
         if (wall & (1u << (i - 1))) {
@@ -173,27 +171,32 @@ __global__ __launch_bounds__(kBlock) void k_adj_boundary(AdjArgs A, const int32_
         nx /= nn;
         ny /= nn;
         nz /= nn;
-        const double fac = -(1.0 - 1.0 / (2.0 * A.tau));
         const double tx = fac * (pxx * nx + pxy * ny + pxz * nz);
         const double ty = fac * (pxy * nx + pyy * ny + pyz * nz);
         const double tz = fac * (pxz * nx + pyz * ny + pzz * nz);
         const double tn = tx * nx + ty * ny + tz * nz;
-        const double sx = tx - tn * nx, sy = ty - tn * ny, sz = tz - tn * nz;
-        const double w = sqrt(sx * sx + sy * sy + sz * sz);
+        sx = tx - tn * nx;
+        sy = ty - tn * ny;
+        sz = tz - tn * nz;
+        w = sqrt(sx * sx + sy * sy + sz * sz);
         jsum = w;
-        if (w > 0.0) {
-          // dWSS/d(g - f^eq)_i = fac (c_i.n)(e.c_i), e = s/|s|; then through f^eq(g)
-          double wd[Q];
-#pragma unroll
-          for (int i = 0; i < Q; ++i)
-            wd[i] = fac * (cx(i) * nx + cy(i) * ny + cz(i) * nz) * (cx(i) * sx + cy(i) * sy + cz(i) * sz) / w;
-          double wa, wbx, wby, wbz;
-          eq_transpose(wd, rho, ux, uy, uz, wa, wbx, wby, wbz);
-#pragma unroll
-          for (int j = 0; j < Q; ++j)
-            m[j] += wd[j] - (wa + wbx * (cx(j) - ux) + wby * (cy(j) - uy) + wbz * (cz(j) - uz));
-        }
       }
+    }
+    // keep the loads of nu below this point: g is dead
+    asm volatile("" ::: "memory");
+    double m[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) m[i] = A.nu[pidx(p32, i)];
+    if (w > 0.0) {
+      // dWSS/d(g - f^eq)_i = fac (c_i.n)(e.c_i), e = s/|s|; then through f^eq(g)
+      double wd[Q];
+#pragma unroll
+      for (int i = 0; i < Q; ++i)
+        wd[i] = fac * (cx(i) * nx + cy(i) * ny + cz(i) * nz) * (cx(i) * sx + cy(i) * sy + cz(i) * sz) / w;
+      double wa, wbx, wby, wbz;
+      eq_transpose(wd, rho, ux, uy, uz, wa, wbx, wby, wbz);
+#pragma unroll
+      for (int j = 0; j < Q; ++j) m[j] += wd[j] - (wa + wbx * (cx(j) - ux) + wby * (cy(j) - uy) + wbz * (cz(j) - uz));
     }
     double dphi = 0.0;  // at the current porosity (also where none is set)
 #pragma unroll
@@ -236,7 +239,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_boundary(AdjArgs A, const int32_
       if (flux) jsum = q;
     }
     A.dphi[p] += dphi;
-    if (wss_on && wall) {
+    if (w > 0.0) {
 #pragma unroll
       for (int i = 0; i < Q; ++i) A.nu[pidx(p32, i)] = m[i];
     }
