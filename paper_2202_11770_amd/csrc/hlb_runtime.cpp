@@ -1301,10 +1301,27 @@ struct Revolve {
   int64_t t0, n, w0, w1, n_snap;
   std::vector<int64_t> slot_t;
   int64_t fwd = 0;
+  // The current state may live in a checkpoint slot instead of the
+  // context's own buffer: a restore only points at the slot, the next forward
+  // step pulls from it into a context buffer (or the adjoint step reads it
+  // there), and a checkpoint's forward run writes its last step straight into
+  // the slot.  No slot is written while it is read, so restores and
+  // checkpoints cost no copy.
+  const void *in_slot = nullptr;
 
-  hlb_status advance(int64_t k) {
+  DevPtrs reading_slot() const {
+    DevPtrs d = c->d;
+    if (in_slot) d.f[c->cur] = const_cast<void *>(in_slot);
+    return d;
+  }
+  // k forward steps; with `last_dst`, the last one writes into that slot.
+  hlb_status advance(int64_t k, void *last_dst = nullptr) {
     for (int64_t s = 0; s < k; ++s) {
-      HIP_TRY(launch_step(c->cfg, c->L, c->d, c->cur, c->t, c->stream, nullptr, nullptr));
+      DevPtrs d = reading_slot();
+      void *dst = (last_dst && s == k - 1) ? last_dst : nullptr;
+      if (dst) d.f[1 - c->cur] = dst;
+      HIP_TRY(launch_step(c->cfg, c->L, d, c->cur, c->t, c->stream, nullptr, nullptr));
+      in_slot = dst;
       c->cur = 1 - c->cur;
       c->t += 1;
     }
@@ -1312,12 +1329,14 @@ struct Revolve {
     return HLB_OK;
   }
   hlb_status save(int64_t slot) {
-    HIP_TRY(hipMemcpyAsync(c->adj_slots[slot], c->d.f[c->cur], buf_bytes(c), hipMemcpyDeviceToDevice, c->stream));
+    const void *src = in_slot ? in_slot : c->d.f[c->cur];
+    if (src != c->adj_slots[slot])
+      HIP_TRY(hipMemcpyAsync(c->adj_slots[slot], src, buf_bytes(c), hipMemcpyDeviceToDevice, c->stream));
     slot_t[slot] = c->t;
     return HLB_OK;
   }
   hlb_status restore(int64_t slot) {
-    HIP_TRY(hipMemcpyAsync(c->d.f[0], c->adj_slots[slot], buf_bytes(c), hipMemcpyDeviceToDevice, c->stream));
+    in_slot = c->adj_slots[slot];
     c->cur = 0;
     c->t = slot_t[slot];
     c->direct = false;
@@ -1337,7 +1356,8 @@ struct Revolve {
       e1 = ts.e[1];
       HIP_TRY(hipEventRecord(e0, c->stream));
     }
-    HIP_TRY(launch_adjoint_step(c->cfg, c->L, c->d, c->cur, t, c->adj, in_window, n, t - 1 - t0, c->stream));
+    HIP_TRY(launch_adjoint_step(c->cfg, c->L, reading_slot(), c->cur, t, c->adj, in_window, n, t - 1 - t0,
+                                c->stream));
     if (e1) HIP_TRY(hipEventRecord(e1, c->stream));
     return HLB_OK;
   }
@@ -1350,8 +1370,8 @@ struct Revolve {
       const int64_t m = b - right;
       const int64_t slot_m = n_snap - cfree;
       if (hlb_status st = restore(slot_a)) return st;
-      if (hlb_status st = advance(m - a)) return st;
-      if (hlb_status st = save(slot_m)) return st;
+      if (hlb_status st = advance(m - a, c->adj_slots[slot_m])) return st;  // m - a >= 1
+      slot_t[slot_m] = c->t;
       if (hlb_status st = reverse(m, b, slot_m, cfree - 1)) return st;
       b = m;
     }
