@@ -18,14 +18,17 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SO = os.path.join(_HERE, "liboracle.so")
+# The mutation tests build altered copies of the sources elsewhere and point
+# the package at them through these two variables.
+_SRC = os.environ.get("HLB_ORACLE_SRC", _HERE)
+_SO = os.environ.get("HLB_ORACLE_LIB", os.path.join(_HERE, "liboracle.so"))
 _lib = None
 Q = 19
 
 
 def build(verbose: bool = False) -> str:
     """Compile liboracle.so (gcc, -O2, no FP contraction, OpenMP)."""
-    srcs = [os.path.join(_HERE, s) for s in ("oracle.c", "oracle_adjoint.c") if os.path.exists(os.path.join(_HERE, s))]
+    srcs = [os.path.join(_SRC, s) for s in ("oracle.c", "oracle_adjoint.c", "oracle_tangent.c")]
     cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC", "-shared",
            *srcs, "-o", _SO, "-lm"]
     if verbose:
@@ -74,8 +77,10 @@ def _load():
 
 def _declare_adjoint(lib):
     P, i64, i32, d = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
-    lib.orc_adj_run.argtypes = [i64, P, P, d, d, P, i32, P, i64, i64, i64, i64, i32, P, P, P, P, P]
+    lib.orc_adj_run.argtypes = [i64, P, P, d, d, P, i32, P, i64, i64, i64, i64, i32, P, P, P, P, P, P]
     lib.orc_adj_run.restype = ctypes.c_int
+    lib.orc_tl_run.argtypes = [i64, P, P, d, d, P, i32, P, i64, i64, i64, i64, i32, P, P, P, P, P, P]
+    lib.orc_tl_run.restype = ctypes.c_int
     lib.orc_iolet_flux.argtypes = [i64, P, P, d, d, P, i32, i64, P, P]
     lib.orc_iolet_flux.restype = ctypes.c_int
 
@@ -159,26 +164,49 @@ class Problem:
     def wss_sum(self, f) -> float:
         return float(_load().orc_wss_sum(self.n, _p(self.nbr), self.tau, _p(np.ascontiguousarray(f))))
 
-    def adjoint(self, f0, t0: int, nsteps: int, obj_t0: int, obj_t1: int, weights=None):
+    def adjoint(self, f0, t0: int, nsteps: int, obj_t0: int, obj_t1: int, weights=None, state_grad=False):
         """Reference adjoint (oracle_adjoint.c).  J = sum over t in (obj_t0,
         obj_t1] of the summed wall shear stress (weights None), or of
         sum_k weights[k] Q_k(t), Q_k(t) the outflow of iolet k during the
         update t-1 -> t (weights [n_io]).  Returns J, the derivatives with
         respect to the per-step iolet table values [n_io][nsteps] (amplitude
-        or ghost density) and the per-site porosity [n].  Keeps all nsteps+1
-        states in memory."""
+        or ghost density) and the per-site porosity [n], and with
+        state_grad also the derivative with respect to f0 [n][19].  Keeps all
+        nsteps+1 states in memory."""
         f0 = np.ascontiguousarray(f0, dtype=np.float64)
         J = np.zeros(1)
         dA = np.zeros((max(self.n_io, 1), nsteps))
         dphi = np.zeros(self.n)
         w = None if weights is None else np.ascontiguousarray(weights, dtype=np.float64)
+        df0 = np.zeros_like(f0) if state_grad else None
         rc = _load().orc_adj_run(self.n, _p(self.coords), _p(self.nbr), self.tau, self.rho0, ctypes.byref(self.io),
                                  self.n_io, _p(self.phi), int(t0), int(nsteps), int(obj_t0), int(obj_t1),
                                  0 if w is None else 1, None if w is None else _p(w), _p(f0),
-                                 _p(J), _p(dA), _p(dphi))
+                                 _p(J), _p(dA), _p(dphi), _p(df0))
         if rc != 0:
             raise ValueError("oracle adjoint failed")
+        if state_grad:
+            return float(J[0]), dA[: self.n_io], dphi, df0
         return float(J[0]), dA[: self.n_io], dphi
+
+    def tangent(self, f0, t0: int, nsteps: int, obj_t0: int, obj_t1: int, weights=None, df0=None, dtab=None,
+                dphi=None) -> float:
+        """Tangent-linear model (oracle_tangent.c): the derivative of the
+        objective of adjoint() in the direction (df0 [n][19], dtab
+        [n_io][nsteps], dphi [n]); each part may be None (zero)."""
+        f0 = np.ascontiguousarray(f0, dtype=np.float64)
+        dJ = np.zeros(1)
+        w = None if weights is None else np.ascontiguousarray(weights, dtype=np.float64)
+        if dtab is not None:
+            dtab = np.ascontiguousarray(dtab, dtype=np.float64)
+            assert dtab.shape == (self.n_io, nsteps)
+        rc = _load().orc_tl_run(self.n, _p(self.coords), _p(self.nbr), self.tau, self.rho0, ctypes.byref(self.io),
+                                self.n_io, _p(self.phi), int(t0), int(nsteps), int(obj_t0), int(obj_t1),
+                                0 if w is None else 1, None if w is None else _p(w), _p(f0), _p(_c64(df0)),
+                                _p(dtab), _p(_c64(dphi)), _p(dJ))
+        if rc != 0:
+            raise ValueError("oracle tangent failed")
+        return float(dJ[0])
 
     def iolet_flux(self, f, t: int) -> np.ndarray:
         """Outflow of each iolet during the update t -> t+1 from the state f at t."""

@@ -21,7 +21,8 @@
  *
  * Extensions the paper does not define, each stated where it is used:
  * wall shear stress, per-wall-site porosity, the mass-balance bookkeeping,
- * and the tangent-linear / adjoint models of oracle_adjoint.c.
+ * and the adjoint and tangent-linear models of oracle_adjoint.c and
+ * oracle_tangent.c.
  *
  * Pins: see tests/test_oracle_*.py.  The velocity-iolet density choice
  * (reference density rho0), the pressure-iolet ghost velocity (site velocity
@@ -115,12 +116,26 @@ void orc_iolet_profile(const orc_iolet *k, const double *m, double *P);
  * respect to the table value iolet k uses at step t0+s (the amplitude A_k of
  * a velocity iolet, the ghost density rho_k of a pressure iolet); dJ_dphi
  * [n]: derivative with respect to each site's porosity (zero at sites without
- * wall links).  phi may be NULL (no porosity, derivative still at phi = 0).
- * Returns 0, or -1 on a bad argument, link code or allocation failure. */
+ * wall links); dJ_df0 [n*19] (may be NULL): derivative with respect to the
+ * initial state f0.  phi may be NULL (no porosity, derivative still at
+ * phi = 0).  Returns 0, or -1 on a bad argument, link code or allocation
+ * failure. */
 int orc_adj_run(int64_t n, const int32_t *coords, const int32_t *nbr, double tau, double rho0,
                 const orc_iolet *io, int32_t n_io, const double *phi, int64_t t0, int64_t nsteps,
                 int64_t obj_t0, int64_t obj_t1, int32_t objective, const double *weights, const double *f0,
-                double *J, double *dJ_dtab, double *dJ_dphi);
+                double *J, double *dJ_dtab, double *dJ_dphi, double *dJ_df0);
+
+/* Tangent-linear model (oracle_tangent.c): the derivative dJ of the
+ * objective of orc_adj_run (same arguments) in the direction given by df0
+ * [n*19] (perturbation of the initial state, may be NULL), dtab
+ * [n_io][nsteps] (perturbation of the table value iolet k uses at step
+ * t0+s, may be NULL) and dphi [n] (porosity perturbation, may be NULL).
+ * Serial.  Returns 0, or -1 on a bad argument, link code or allocation
+ * failure. */
+int orc_tl_run(int64_t n, const int32_t *coords, const int32_t *nbr, double tau, double rho0,
+               const orc_iolet *io, int32_t n_io, const double *phi, int64_t t0, int64_t nsteps,
+               int64_t obj_t0, int64_t obj_t1, int32_t objective, const double *weights, const double *f0,
+               const double *df0, const double *dtab, const double *dphi, double *dJ);
 
 /* Number of OpenMP threads the oracle uses. */
 int32_t orc_threads(void);

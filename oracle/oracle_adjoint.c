@@ -196,7 +196,7 @@ static int adj_step(int64_t n, const int32_t *coords, const int32_t *nbr, double
 int orc_adj_run(int64_t n, const int32_t *coords, const int32_t *nbr, double tau, double rho0,
                 const orc_iolet *io, int32_t n_io, const double *phi, int64_t t0, int64_t nsteps,
                 int64_t obj_t0, int64_t obj_t1, int32_t objective, const double *weights, const double *f0,
-                double *J, double *dJ_dA, double *dJ_dphi) {
+                double *J, double *dJ_dA, double *dJ_dphi, double *dJ_df0) {
   if (objective != 0 && (objective != 1 || (n_io > 0 && !weights))) return -1;
   const int wss = objective == 0;
   lattice_init();
@@ -273,6 +273,7 @@ int orc_adj_run(int64_t n, const int32_t *coords, const int32_t *nbr, double tau
     mu = mu2;
     mu2 = tmp;
   }
+  if (dJ_df0) memcpy(dJ_df0, mu, sizeof(double) * sz);
   free(F); free(mu); free(mu2); free(gr); free(dA);
   return 0;
 }

@@ -14,6 +14,10 @@ Every check here is fixed by something other than the oracle's code:
   ghost-density pressure iolet and eq. (8));
 * the straight-pipe configuration: Poiseuille profile, pressure drop, flux
   and wall shear stress (pins the wall shear stress definition's scale);
+* porous walls: a box whose walls all leak to the reservoir reaches the
+  reservoir state (rho0, at rest) exactly; with a small porosity the box
+  stays well mixed and its mean density relaxes exponentially at the rate
+  phi * (sum of the weights of its wall links) / (number of sites);
 * permutation invariance of the site numbering.
 """
 import math
@@ -233,3 +237,34 @@ def test_permutation_invariance(orc):
     P.run(f, 0, 50)
     Pp.run(fp, 0, 50)
     assert np.array_equal(f[perm], fp)
+
+
+def test_porous_box_relaxes_to_reservoir(orc):
+    g = G.sealed_box(8)
+    ws = g.wall_sites()
+    rho0 = 0.99
+    # every wall link leaks completely: the only steady state is the reservoir's
+    phi = np.zeros(g.n)
+    phi[ws] = 1.0
+    P = orc.Problem(g, 0.8, rho0=rho0, phi=phi)
+    rng = np.random.default_rng(1)
+    f = P.init(1.0 + 0.01 * rng.uniform(-1, 1, g.n), 0.01 * rng.uniform(-1, 1, (g.n, 3)))
+    P.run(f, 0, 400)
+    rho, u, _ = P.macros(f)
+    assert np.abs(rho - rho0).max() <= 1e-13 and np.abs(u).max() <= 1e-13
+    # a slow leak: the box mixes much faster than it drains, so its mean
+    # density follows rho0 + (rho_1 - rho0) exp(-kappa t) with kappa = phi *
+    # (sum over wall links of w_i) / N, up to O(phi) mixing corrections
+    _, w, _ = orc.lattice()
+    ph = 1e-3
+    phi[ws] = ph
+    P = orc.Problem(g, 0.8, rho0=rho0, phi=phi)
+    f = P.init(np.ones(g.n), None)
+    links = g.nbr[:, 1:] == G.LINK_WALL
+    kappa = ph * float((links * w[None, 1:]).sum()) / g.n
+    T = 3000
+    P.run(f, 0, T)
+    mean = P.mass(f) / g.n
+    pred = rho0 + (1.0 - rho0) * math.exp(-kappa * T)
+    print(f"mean density {mean:.12f}, well-mixed prediction {pred:.12f}")
+    assert abs((mean - rho0) / (pred - rho0) - 1.0) <= 1e-3
