@@ -103,11 +103,12 @@ def stored_traffic(storage, n_sites):
     return None
 
 
-def run_storage(g, tables, tau, storage, steps, warmup, scheme="pull", windkessel=None):
+def run_storage(g, tables, tau, storage, steps, warmup, scheme="pull", windkessel=None, sites_per_thread=0):
     import torch
     from paper_2202_11770_amd import hlb
     t0 = time.time()
-    sim = hlb.Simulation.create(g, tau, storage=storage, tables=tables, scheme=scheme)
+    sim = hlb.Simulation.create(g, tau, storage=storage, tables=tables, scheme=scheme,
+                                sites_per_thread=sites_per_thread)
     for k, m in (windkessel or {}).items():
         hlb.hlb_set_windkessel(sim.ctx, k, m)
     info = sim.info()
@@ -335,6 +336,9 @@ def main():
     ap.add_argument("--no-copy", action="store_true")
     ap.add_argument("--schemes", default="pull",
                     help="update orders to time: pull (the headline), and push for the A/B")
+    ap.add_argument("--sites-per-thread", default="0",
+                    help="bulk sites per GPU thread, comma-separated: the first value is timed as the headline "
+                         "(0: the library's default per storage), the others as an A/B")
     ap.add_argument("--adjoint", action="store_true",
                     help="also time the adjoint's reverse step on the workload (FP64)")
     ap.add_argument("--oracle-table", action="store_true",
@@ -360,10 +364,11 @@ def main():
     g, tables = workload(args.workload)
     log(f"workload: {args.workload}: {g.n} sites, {len(g.iolets)} iolets, fill {g.meta['fill']:.4f}, "
         f"generated in {time.time() - t0:.1f}s")
+    spts = [int(x) for x in args.sites_per_thread.split(",") if x]
     results = {}
     for st in args.storages.split(","):
         t1 = time.time()
-        results[st] = run_storage(g, tables, tau, st, args.steps, args.warmup)
+        results[st] = run_storage(g, tables, tau, st, args.steps, args.warmup, sites_per_thread=spts[0])
         r = results[st]
         log(f"{st}: {r['mlups']:.0f} MLUPS, {r['ms_per_step']:.3f} ms/step, step kernel {r['kernel_ms']:.3f} ms "
             f"= {r['kernel_gbs']:.0f} GB/s ({100 * r['frac']:.1f}% of 8 TB/s), mass residual {r['mass_residual_rel']:.2e} "
@@ -381,6 +386,16 @@ def main():
                            "mass_residual_rel": r["mass_residual_rel"]}
             log(f"{sch} {st}: {r['mlups']:.0f} MLUPS, step kernel {r['kernel_ms']:.3f} ms = {r['kernel_gbs']:.0f} GB/s "
                 f"({100 * r['frac']:.1f}%), {ab[sch][st]['vs_pull']:.3f}x pull")
+    spt_ab = {}
+    for spt in spts[1:]:
+        spt_ab[str(spt)] = {}
+        for st in args.storages.split(","):
+            r = run_storage(g, tables, tau, st, args.steps, args.warmup, sites_per_thread=spt)
+            spt_ab[str(spt)][st] = {"mlups": round(r["mlups"], 1), "kernel_ms": round(r["kernel_ms"], 5),
+                                    "kernel_gbs": round(r["kernel_gbs"], 1), "frac": round(r["frac"], 4),
+                                    "vs_headline": round(r["mlups"] / results[st]["mlups"], 3)}
+            log(f"sites_per_thread {spt} {st}: {r['mlups']:.0f} MLUPS, step kernel {r['kernel_ms']:.3f} ms = "
+                f"{r['kernel_gbs']:.0f} GB/s ({100 * r['frac']:.1f}%), {spt_ab[str(spt)][st]['vs_headline']:.3f}x")
     copy_gbs = None if args.no_copy else round(copy_ceiling(), 1)
     if copy_gbs:
         log(f"plain copy: {copy_gbs:.0f} GB/s")
@@ -447,6 +462,8 @@ def main():
         out["errors_vs_f64_gpu"] = {"steps": args.compare_steps, **compare}
     if ab:
         out["schemes"] = ab
+    if spt_ab:
+        out["sites_per_thread_ab"] = spt_ab
     if split:
         out["split"] = split
     if wk:

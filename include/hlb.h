@@ -123,6 +123,10 @@ typedef struct {
   double rho0;         /* reference density (default 1.0) */
   int64_t max_device_bytes; /* 0: no limit; otherwise HLB_ENOMEM above it */
   int32_t scheme;      /* HLB_SCHEME_PULL (default) or HLB_SCHEME_PUSH */
+  int32_t sites_per_thread; /* bulk+wall sites per GPU thread in the full pull
+                               step: 1 or 2; 0 (default): the measured best
+                               for the storage type.  Results do not depend
+                               on it. */
 } hlb_options;
 
 /* Order of the fused update (Sec. 3.2 implements push and names pull as

@@ -330,6 +330,55 @@ __device__ inline C gather(const T *__restrict__ A, int64_t p, int64_t blk, cons
   return flux;
 }
 
+// Two bulk+wall sites at once (gather<false, ...> for p and p2): both offset
+// rows are fetched, then all 38 population loads are issued before any is
+// used (the scheduling barrier keeps the compiler from interleaving the two
+// sites' loads with the first site's arithmetic), so that a wavefront has
+// twice the bytes in flight of the one-site form.  Returns the porous-wall
+// flux of each site in flux1 / flux2.
+template <bool POROUS, bool SH, bool NARROW, typename T, typename C>
+__device__ inline void gather_bulk2(const T *__restrict__ A, int64_t p, int64_t blk, int64_t p2, int64_t blk2,
+                                    const GatherArgs &a, C (&g)[Q], C (&h)[Q], C &flux1, C &flux2) {
+  const int64_t np = a.np;
+  int32_t o1[Q - 1], o2[Q - 1];
+  bulk_offsets(a, p, blk, o1);
+  bulk_offsets(a, p2, blk2, o2);
+  const int32_t q1 = (int32_t)p, q2 = (int32_t)p2;
+  uint32_t wall1 = 0, wall2 = 0;
+  g[0] = ld(at<NARROW>(A, q1, 0));
+  h[0] = ld(at<NARROW>(A, q2, 0));
+#pragma unroll
+  for (int i = 1; i < Q; ++i) {
+    const int32_t j1 = q1 + o1[i - 1], j2 = q2 + o2[i - 1];
+    const bool w1 = (uint32_t)j1 >= (uint32_t)np, w2 = (uint32_t)j2 >= (uint32_t)np;
+    g[i] = ld(at<NARROW>(A, w1 ? q1 : j1, w1 ? opp(i) : i));
+    h[i] = ld(at<NARROW>(A, w2 ? q2 : j2, w2 ? opp(i) : i));
+    if constexpr (POROUS) {
+      wall1 |= (uint32_t)w1 << i;
+      wall2 |= (uint32_t)w2 << i;
+    }
+  }
+  __builtin_amdgcn_sched_barrier(0);
+  flux1 = 0;
+  flux2 = 0;
+  if constexpr (POROUS) {
+    const C ph1 = C(a.phi[p]), ph2 = C(a.phi[p2]);
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+      if ((wall1 >> i) & 1u) {
+        const C nv = g[i] - ph1 * (g[i] - rest<SH, C>(i, C(a.rho0)));
+        flux1 += nv - g[i];
+        g[i] = nv;
+      }
+      if ((wall2 >> i) & 1u) {
+        const C nv = h[i] - ph2 * (h[i] - rest<SH, C>(i, C(a.rho0)));
+        flux2 += nv - h[i];
+        h[i] = nv;
+      }
+    }
+  }
+}
+
 // Push order (the paper's implementation): site p has collided its own
 // pre-collision state into fp (post-collision, stored representation); each
 // population j goes where it arrives at t+1 -- slot j of the site at

@@ -92,7 +92,12 @@ struct LaunchCfg {
   int xcd_chunk = 0;  // blocks per XCD chunk (0: plain block order)
   bool porous = false;
   int scheme = HLB_SCHEME_PULL;
+  int sites_per_thread = 1;  // bulk+wall sites per thread in the full pull step (1 or 2)
 };
+
+// Bulk+wall sites per thread of the full pull step for a storage type when
+// the caller leaves it open (the measured best).
+int default_sites_per_thread(int storage);
 
 // ---- launchers (hlb_kernels.hip); all asynchronous on `s` ----
 // One update t -> t+1: reads buffer `src`, writes buffer 1-src.

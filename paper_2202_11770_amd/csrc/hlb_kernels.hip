@@ -42,16 +42,23 @@ using namespace dev;
 // offsets when a buffer allows it (see at()).  FP64: the natural 4 waves and
 // 32-bit offsets; FP32: the natural 5 waves and 64-bit addresses (32-bit
 // offsets measured 3% slower); FP16: 8 waves and 32-bit offsets.
-template <typename T>
-constexpr int kStepWaves = std::is_same<T, double>::value ? 4 : (std::is_same<T, float>::value ? 5 : 8);
+// SPT = 2 (two bulk+wall sites per thread, see below) needs about twice the
+// registers of the bulk path: 4 waves.
+template <typename T, int SPT = 1>
+constexpr int kStepWaves =
+    SPT == 2 ? 4 : (std::is_same<T, double>::value ? 4 : (std::is_same<T, float>::value ? 5 : 8));
 template <typename T>
 constexpr bool kStepNarrow = !std::is_same<T, float>::value;
 
-template <typename T, bool POROUS, bool NARROW>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kStepWaves<T>, 8))) void k_step(const T *__restrict__ A, T *__restrict__ B, GatherArgs a,
-                                                 const int32_t *__restrict__ order, int64_t n0, int64_t nb_io,
-                                                 int64_t blk0, int64_t nb_bulk, int xcd_chunk,
-                                                 typename Acc<T>::type omega, double *acc) {
+// SPT: bulk+wall sites per thread.  With SPT = 2 a workgroup takes two
+// consecutive 256-position blocks and each thread one position of each (both
+// coalesced); the two sites' table loads and 36 gathers are all issued
+// before either collides, which doubles the bytes a wavefront has in flight.
+// nb_bulk then counts block pairs.  Only the full step (blk0 = 0) uses it.
+template <typename T, bool POROUS, bool NARROW, int SPT = 1>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kStepWaves<T, SPT>, 8))) void k_step(
+    const T *__restrict__ A, T *__restrict__ B, GatherArgs a, const int32_t *__restrict__ order, int64_t n0,
+    int64_t nb_io, int64_t blk0, int64_t nb_bulk, int xcd_chunk, typename Acc<T>::type omega, double *acc) {
   using C = typename Acc<T>::type;
   constexpr bool SH = kShifted<T>;
   const int64_t b = blockIdx.x;
@@ -69,7 +76,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kStepWav
     const double s = wave_sum(double(flux));
     if ((threadIdx.x & 63) == 0 && s != 0.0) atomicAdd(acc, s);
     if (a.io_flux) wave_add_grouped(a.io_flux, wkf);
-  } else {
+  } else if constexpr (SPT == 1) {
     const int64_t blk = blk0 + block_id(b - nb_io, nb_bulk, xcd_chunk);
     const int64_t p = blk * kBlock + threadIdx.x;
     if (p < n0) {
@@ -78,6 +85,30 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kStepWav
       collide<SH>(g, omega, C(a.rho0));
 #pragma unroll
       for (int i = 0; i < Q; ++i) st(at<NARROW>(B, (int32_t)p, i), g[i]);
+    }
+    if constexpr (POROUS) {
+      const double s = wave_sum(double(flux));
+      if ((threadIdx.x & 63) == 0 && s != 0.0) atomicAdd(acc, s);
+    }
+  } else {
+    const int64_t blk = 2 * block_id(b - nb_io, nb_bulk, xcd_chunk);
+    const int64_t p = blk * kBlock + threadIdx.x;
+    if (p < n0) {
+      // the second site; past the group's end (last pair only) it repeats
+      // the first and stores the same values again (a conditional store
+      // would let the compiler sink the second site's loads behind the
+      // first site's stores)
+      const bool has2 = p + kBlock < n0;
+      const int64_t p2 = has2 ? p + kBlock : p, blk2 = has2 ? blk + 1 : blk;
+      C g[Q], h[Q], flux2;
+      gather_bulk2<POROUS, SH, NARROW>(A, p, blk, p2, blk2, a, g, h, flux, flux2);
+      if (has2) flux += flux2;
+      collide<SH>(g, omega, C(a.rho0));
+      collide<SH>(h, omega, C(a.rho0));
+#pragma unroll
+      for (int i = 0; i < Q; ++i) st(at<NARROW>(B, (int32_t)p, i), g[i]);
+#pragma unroll
+      for (int i = 0; i < Q; ++i) st(at<NARROW>(B, (int32_t)p2, i), h[i]);
     }
     if constexpr (POROUS) {
       const double s = wave_sum(double(flux));
@@ -348,7 +379,10 @@ hipError_t step_impl(const LaunchCfg &cfg, const Layout &L, const DevPtrs &d, in
   const int64_t nb_io = part == 2 ? 0 : (L.nio + kBlock - 1) / kBlock;
   const int64_t blk0 = part == 2 ? L.edge_blocks : 0;
   const int64_t nb_bulk = part == 0 ? nb_all : (part == 1 ? L.edge_blocks : nb_all - L.edge_blocks);
-  const unsigned grid = (unsigned)(nb_io + nb_bulk);
+  // two bulk+wall sites per thread: full pull steps only
+  const bool pair = cfg.sites_per_thread == 2 && part == 0 && cfg.scheme == HLB_SCHEME_PULL;
+  const int64_t nb_launch = pair ? (nb_bulk + 1) / 2 : nb_bulk;
+  const unsigned grid = (unsigned)(nb_io + nb_launch);
   hipError_t er;
   if (e0 && (er = hipEventRecord(e0, s)) != hipSuccess) return er;
   // byte offsets fit in 32 bits when a whole population buffer does
@@ -359,6 +393,9 @@ hipError_t step_impl(const LaunchCfg &cfg, const Layout &L, const DevPtrs &d, in
     if (cfg.scheme == HLB_SCHEME_PUSH)                                                                  \
       k_step_push<T, P, N><<<grid, kBlock, 0, s>>>(A, B, a, d.order, n0, nb_io, blk0, nb_bulk,          \
                                                    cfg.xcd_chunk, omega, d.acc);                        \
+    else if (pair)                                                                                      \
+      k_step<T, P, N, 2><<<grid, kBlock, 0, s>>>(A, B, a, d.order, n0, nb_io, 0, nb_launch,             \
+                                                 cfg.xcd_chunk, omega, d.acc);                          \
     else                                                                                                \
       k_step<T, P, N><<<grid, kBlock, 0, s>>>(A, B, a, d.order, n0, nb_io, blk0, nb_bulk, cfg.xcd_chunk, \
                                               omega, d.acc);                                            \
@@ -459,6 +496,11 @@ hipError_t mass_impl(const Layout &L, const DevPtrs &d, int src, hipStream_t s) 
     case HLB_F16_SHIFTED: { using T = _Float16; return CALL; } \
     default: return hipErrorInvalidValue;                 \
   }
+
+int default_sites_per_thread(int storage) {
+  (void)storage;
+  return 1;
+}
 
 hipError_t launch_step(const LaunchCfg &cfg, const Layout &L, const DevPtrs &d, int src, int64_t t,
                        hipStream_t s, hipEvent_t e0, hipEvent_t e1, int part) {

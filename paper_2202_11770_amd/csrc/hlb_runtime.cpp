@@ -326,6 +326,7 @@ hlb_status hlb_default_options(hlb_options *opt) {
   opt->rho0 = 1.0;
   opt->max_device_bytes = 0;
   opt->scheme = HLB_SCHEME_PULL;
+  opt->sites_per_thread = 0;
   return HLB_OK;
 }
 
@@ -352,6 +353,8 @@ static hlb_status create_impl(int64_t n, const int32_t *coords, const uint8_t *t
     return fail(HLB_EINVAL, "bad options");
   if (opt.adjoint && opt.storage != HLB_F64) return fail(HLB_EINVAL, "the adjoint needs FP64 storage");
   if (opt.scheme != HLB_SCHEME_PULL && opt.scheme != HLB_SCHEME_PUSH) return fail(HLB_EINVAL, "bad scheme %d", opt.scheme);
+  if (opt.sites_per_thread < 0 || opt.sites_per_thread > 2)
+    return fail(HLB_EINVAL, "sites_per_thread must be 0, 1 or 2 (got %d)", opt.sites_per_thread);
   if (opt.adjoint && opt.scheme != HLB_SCHEME_PULL) return fail(HLB_EINVAL, "the adjoint needs the pull scheme");
   int64_t n_ghost = 0;
   if (role) {
@@ -439,6 +442,7 @@ static hlb_status create_impl(int64_t n, const int32_t *coords, const uint8_t *t
   c->cfg.xcd_chunk = opt.xcd_remap;
   c->cfg.porous = false;
   c->cfg.scheme = opt.scheme;
+  c->cfg.sites_per_thread = opt.sites_per_thread > 0 ? opt.sites_per_thread : default_sites_per_thread(opt.storage);
   c->order = opt.order;
   c->max_bytes = opt.max_device_bytes;
   c->iolets.assign(iolets, iolets + n_iolets);

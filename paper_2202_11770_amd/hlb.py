@@ -48,7 +48,7 @@ class hlb_iolet(ctypes.Structure):
 class hlb_options(ctypes.Structure):
     _fields_ = [("storage", ctypes.c_int32), ("order", ctypes.c_int32), ("xcd_remap", ctypes.c_int32),
                 ("adjoint", ctypes.c_int32), ("rho0", ctypes.c_double), ("max_device_bytes", ctypes.c_int64),
-                ("scheme", ctypes.c_int32)]
+                ("scheme", ctypes.c_int32), ("sites_per_thread", ctypes.c_int32)]
 
 
 class hlb_windkessel(ctypes.Structure):
@@ -443,9 +443,10 @@ class Simulation:
     @classmethod
     def create(cls, geom, tau: float, storage: str = "f64", order: str = "lex", xcd_remap: int = 8,
                rho0: float = 1.0, max_device_bytes: int = 0, tables=None, adjoint: bool = False,
-               scheme: str = "pull"):
+               scheme: str = "pull", sites_per_thread: int = 0):
         opt = hlb_default_options()
         opt.scheme = SCHEME[scheme]
+        opt.sites_per_thread = int(sites_per_thread)
         opt.storage = STORAGE[storage]
         opt.order = ORDER[order]
         opt.xcd_remap = int(xcd_remap)
