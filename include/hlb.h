@@ -127,6 +127,15 @@ typedef struct {
                                step: 1 or 2; 0 (default): the measured best
                                for the storage type.  Results do not depend
                                on it. */
+  int32_t graph_steps; /* k > 0 (even, up to 4096): hlb_step replays a
+                          captured HIP graph of k steps for as many whole
+                          graphs as fit and launches the rest one by one;
+                          0 (default): every step is its own launch.  A
+                          graph is recaptured when a buffer, table pointer,
+                          porosity or Windkessel setting changes; it is not
+                          used while timing is on.  Results do not depend on
+                          it (bit for bit, except where atomics already make
+                          the Windkessel outflow order-dependent). */
 } hlb_options;
 
 /* Order of the fused update (Sec. 3.2 implements push and names pull as
@@ -232,6 +241,8 @@ typedef struct {
   int32_t adjoint;          /* hlb_adjoint_run enabled (opt.adjoint) */
   int32_t porous;           /* a porosity field is set */
   int32_t scheme;           /* hlb_scheme of the context */
+  int32_t sites_per_thread; /* bulk+wall sites per thread of the full pull step */
+  int32_t graph_steps;      /* steps per replayed graph in hlb_step (0: none) */
 } hlb_info_t;
 hlb_status hlb_info(const hlb_ctx *ctx, hlb_info_t *info);
 

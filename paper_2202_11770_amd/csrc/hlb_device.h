@@ -205,9 +205,13 @@ struct GatherArgs {
   const double *wk_rho;  // Windkessel outlet densities [n_iolets][2] by time parity
   double *io_flux;       // outflow accumulators of Windkessel outlets, or null (no accumulation)
   int64_t t;           // the update t -> t+1 uses the tables at t
+  const int64_t *t_base;  // non-null inside a replayed graph: the time is *t_base + t
   const double *phi;   // porosity or null
   double rho0;
 };
+
+// Time of the update an iolet rule belongs to (see GatherArgs::t_base).
+__device__ inline int64_t step_time(const GatherArgs &a) { return a.t_base ? *a.t_base + a.t : a.t; }
 
 static_assert(kBlock == kSegBlock, "one segment base per workgroup");
 static_assert(kSegRow == 20, "segment rows are five 16-byte vectors");
@@ -294,6 +298,7 @@ __device__ inline C gather(const T *__restrict__ A, int64_t p, int64_t blk, cons
     // being kept live with the 19 gathered ones: the empty asm hides that
     // q == p, so the compiler cannot merge those reads with the ones above
     // and keep 19 more registers for them.
+    const int64_t t = step_time(a);
     int32_t q = (int32_t)p;
     asm volatile("" : "+v"(q));
     g[0] = ld(at<NARROW>(A, q, 0));
@@ -312,7 +317,7 @@ __device__ inline C gather(const T *__restrict__ A, int64_t p, int64_t blk, cons
       } else {
         const int k = -code - 2;
         const IoletDev K = a.io[k];
-        const double val = K.wk ? a.wk_rho[2 * k + (a.t & 1)] : a.tables[K.tab_off + a.t % K.tab_len];
+        const double val = K.wk ? a.wk_rho[2 * k + (t & 1)] : a.tables[K.tab_off + t % K.tab_len];
         if (K.kind == HLB_IOLET_VELOCITY) {
           v = back + C(a.corr[(int64_t)(i - 1) * a.nio + (p - a.io_begin)] * val);
         } else {
@@ -413,6 +418,7 @@ __device__ inline C scatter(T *__restrict__ B, int64_t p, int64_t blk, const Gat
       st_cached(at<NARROW>(B, wall ? p32 : q, wall ? opp(j) : j), v);
     }
   } else {
+    const int64_t t = step_time(a);
 #pragma unroll
     for (int j = 1; j < Q; ++j) {
       const int i = opp(j);  // the direction the boundary fills at p
@@ -429,7 +435,7 @@ __device__ inline C scatter(T *__restrict__ B, int64_t p, int64_t blk, const Gat
       } else {
         const int k = -code - 2;
         const IoletDev K = a.io[k];
-        const double val = K.wk ? a.wk_rho[2 * k + (a.t & 1)] : a.tables[K.tab_off + a.t % K.tab_len];
+        const double val = K.wk ? a.wk_rho[2 * k + (t & 1)] : a.tables[K.tab_off + t % K.tab_len];
         if (K.kind == HLB_IOLET_VELOCITY) {
           v = back + C(a.corr[(int64_t)(i - 1) * a.nio + (p - a.io_begin)] * val);
         } else {
@@ -462,6 +468,7 @@ inline GatherArgs make_args(const LaunchCfg &cfg, const Layout &L, const DevPtrs
   a.wk_rho = d.wk_rho;
   a.io_flux = d.io_flux;
   a.t = t;
+  a.t_base = d.t_base;
   a.phi = cfg.porous ? d.phi : nullptr;
   a.rho0 = cfg.rho0;
   return a;

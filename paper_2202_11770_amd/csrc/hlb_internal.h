@@ -83,6 +83,10 @@ struct DevPtrs {
   double *wk_rho = nullptr;         // [n_iolets][2] Windkessel densities by time parity
   double *io_flux = nullptr;        // [n_iolets] outflow of the current update (Windkessel outlets)
   WkParams *wk = nullptr;           // [n_iolets]
+  // Set only in the copies a replayed graph is captured with: the kernels
+  // then take the time as *t_base + t (t = the step's index in the graph),
+  // so that one graph serves every starting time.
+  const int64_t *t_base = nullptr;
 };
 
 struct LaunchCfg {
@@ -148,6 +152,10 @@ hipError_t launch_zero(double *p, int64_t n, hipStream_t s);
 // their state and set the density of the update t+1 -> t+2; the outflow
 // accumulators are cleared (no memset: the launch may be graph-captured).
 hipError_t launch_windkessel(const DevPtrs &d, int n_io, int64_t t, hipStream_t s);
+// *p = v, and *p += k (one thread each; a kernel, not a memset, so that the
+// second can sit in a captured graph).
+hipError_t launch_set_time(int64_t *p, int64_t v, hipStream_t s);
+hipError_t launch_add_time(int64_t *p, int64_t k, hipStream_t s);
 // Sum of the stored deviations of buffer `src` into d.partial[0] (FP64).
 hipError_t launch_mass(const LaunchCfg &cfg, const Layout &L, const DevPtrs &d, int src,
                        hipStream_t s);

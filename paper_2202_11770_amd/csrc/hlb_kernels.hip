@@ -340,11 +340,12 @@ __global__ __launch_bounds__(kBlock) void k_mass_final(double *partial, int64_t 
   }
 }
 
-// One thread per iolet (see launch_windkessel).
+// One thread per iolet (see launch_windkessel).  t_base: as in GatherArgs.
 __global__ void k_windkessel(const IoletDev *io, WkParams *wk, double *wk_rho, double *io_flux, int n_io,
-                             int64_t t) {
+                             int64_t t, const int64_t *t_base) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n_io || !io[k].wk) return;
+  if (t_base) t += *t_base;
   const double Q = io_flux[k];
   io_flux[k] = 0.0;
   WkParams P = wk[k];
@@ -356,6 +357,9 @@ __global__ void k_windkessel(const IoletDev *io, WkParams *wk, double *wk_rho, d
   wk[k] = P;
   wk_rho[2 * k + ((t + 1) & 1)] = P.rho_ref + P.R1 * Q + P.X;
 }
+
+__global__ void k_set_time(int64_t *p, int64_t v) { *p = v; }
+__global__ void k_add_time(int64_t *p, int64_t k) { *p += k; }
 
 __global__ void k_zero(double *p, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -529,7 +533,17 @@ hipError_t launch_set_state(const LaunchCfg &cfg, const Layout &L, const DevPtrs
 
 hipError_t launch_windkessel(const DevPtrs &d, int n_io, int64_t t, hipStream_t s) {
   if (n_io <= 0 || !d.wk) return hipSuccess;
-  k_windkessel<<<(n_io + 63) / 64, 64, 0, s>>>(d.io, d.wk, d.wk_rho, d.io_flux, n_io, t);
+  k_windkessel<<<(n_io + 63) / 64, 64, 0, s>>>(d.io, d.wk, d.wk_rho, d.io_flux, n_io, t, d.t_base);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_time(int64_t *p, int64_t v, hipStream_t s) {
+  k_set_time<<<1, 1, 0, s>>>(p, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_add_time(int64_t *p, int64_t k, hipStream_t s) {
+  k_add_time<<<1, 1, 0, s>>>(p, k);
   return hipGetLastError();
 }
 

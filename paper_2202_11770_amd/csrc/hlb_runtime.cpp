@@ -116,6 +116,19 @@ struct TimedStep {
   hipEvent_t e[2];
 };
 
+// Everything a captured step graph bakes into its kernel arguments: a graph
+// is replayed only while all of it is unchanged.
+bool same_launch(const DevPtrs &a, const DevPtrs &b) {
+  return a.f[0] == b.f[0] && a.f[1] == b.f[1] && a.seg_off == b.seg_off && a.seg_base == b.seg_base &&
+         a.seg_delta == b.seg_delta && a.nbr_io == b.nbr_io && a.order == b.order && a.corr == b.corr &&
+         a.io == b.io && a.tables == b.tables && a.phi == b.phi && a.acc == b.acc && a.wk_rho == b.wk_rho &&
+         a.io_flux == b.io_flux && a.wk == b.wk;
+}
+bool same_launch(const LaunchCfg &a, const LaunchCfg &b) {
+  return a.storage == b.storage && a.tau == b.tau && a.rho0 == b.rho0 && a.xcd_chunk == b.xcd_chunk &&
+         a.porous == b.porous && a.scheme == b.scheme && a.sites_per_thread == b.sites_per_thread;
+}
+
 }  // namespace
 
 struct hlb_ctx {
@@ -178,6 +191,15 @@ struct hlb_ctx {
   AdjBuffers adj;
   int64_t adj_dA_len = 0;
   std::vector<void *> adj_slots;  // checkpoint buffers (post-collision state)
+  // replayed step graphs (hlb_step): one per starting buffer, captured with
+  // the time read from t_dev
+  int graph_steps = 0;            // steps per graph; 0: no graphs
+  int64_t *t_dev = nullptr;       // [1] time at the start of the next replay
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t graph[2] = {nullptr, nullptr};
+  DevPtrs graph_d;                // what the graphs were captured with
+  LaunchCfg graph_cfg;
+  int graph_nwk = -1;
 };
 
 namespace {
@@ -223,6 +245,13 @@ void free_all(hlb_ctx *c) {
     for (auto &e : ts.e) (void)hipEventDestroy(e);
   c->adj_pool.clear();
   c->pool.clear();
+  for (auto &g : c->graph)
+    if (g) (void)hipGraphExecDestroy(g);
+  c->graph[0] = c->graph[1] = nullptr;
+  F(c->t_dev);
+  c->t_dev = nullptr;
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+  c->cap_stream = nullptr;
   if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
   c->d = DevPtrs();
 }
@@ -327,6 +356,7 @@ hlb_status hlb_default_options(hlb_options *opt) {
   opt->max_device_bytes = 0;
   opt->scheme = HLB_SCHEME_PULL;
   opt->sites_per_thread = 0;
+  opt->graph_steps = 0;
   return HLB_OK;
 }
 
@@ -355,6 +385,8 @@ static hlb_status create_impl(int64_t n, const int32_t *coords, const uint8_t *t
   if (opt.scheme != HLB_SCHEME_PULL && opt.scheme != HLB_SCHEME_PUSH) return fail(HLB_EINVAL, "bad scheme %d", opt.scheme);
   if (opt.sites_per_thread < 0 || opt.sites_per_thread > 2)
     return fail(HLB_EINVAL, "sites_per_thread must be 0, 1 or 2 (got %d)", opt.sites_per_thread);
+  if (opt.graph_steps < 0 || opt.graph_steps % 2 != 0 || opt.graph_steps > 4096)
+    return fail(HLB_EINVAL, "graph_steps must be 0 or even in 2..4096 (got %d)", opt.graph_steps);
   if (opt.adjoint && opt.scheme != HLB_SCHEME_PULL) return fail(HLB_EINVAL, "the adjoint needs the pull scheme");
   int64_t n_ghost = 0;
   if (role) {
@@ -443,6 +475,7 @@ static hlb_status create_impl(int64_t n, const int32_t *coords, const uint8_t *t
   c->cfg.porous = false;
   c->cfg.scheme = opt.scheme;
   c->cfg.sites_per_thread = opt.sites_per_thread > 0 ? opt.sites_per_thread : default_sites_per_thread(opt.storage);
+  c->graph_steps = opt.graph_steps;
   c->order = opt.order;
   c->max_bytes = opt.max_device_bytes;
   c->iolets.assign(iolets, iolets + n_iolets);
@@ -985,11 +1018,75 @@ static void macro_source(const hlb_ctx *c, int *src, bool *direct) {
   }
 }
 
+namespace {
+
+// Capture the graph of c->graph_steps steps that starts from buffer `cur`:
+// step k reads the time as *t_dev + k, and a last node advances *t_dev, so
+// that back-to-back replays continue the count.  Captured on a private
+// stream (the context stream may be the null stream, which cannot capture).
+hlb_status capture_steps(hlb_ctx *c, int cur) {
+  if (!c->t_dev) {
+    void *p = nullptr;
+    if (hlb_status st = dev_alloc(c, &p, sizeof(int64_t))) return st;
+    c->t_dev = static_cast<int64_t *>(p);
+  }
+  if (!c->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+  DevPtrs d = c->d;
+  d.t_base = c->t_dev;
+  HIP_TRY(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+  hipError_t e = hipSuccess;
+  for (int k = 0; k < c->graph_steps && e == hipSuccess; ++k) {
+    e = launch_step(c->cfg, c->L, d, (cur + k) & 1, k, c->cap_stream, nullptr, nullptr);
+    if (e == hipSuccess && c->n_wk > 0) e = launch_windkessel(d, (int)c->iolets.size(), k, c->cap_stream);
+  }
+  if (e == hipSuccess) e = launch_add_time(c->t_dev, c->graph_steps, c->cap_stream);
+  hipGraph_t g = nullptr;
+  const hipError_t e2 = hipStreamEndCapture(c->cap_stream, &g);
+  if (e == hipSuccess) e = e2;
+  if (e == hipSuccess) e = hipGraphInstantiate(&c->graph[cur], g, nullptr, nullptr, 0);
+  if (g) (void)hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    c->graph[cur] = nullptr;
+    return fail(HLB_EDEVICE, "capturing the step graph: %s", hipGetErrorString(e));
+  }
+  return HLB_OK;
+}
+
+// reps replays of the step graph from the current time and buffer.
+hlb_status replay_steps(hlb_ctx *c, int64_t reps) {
+  if (!same_launch(c->graph_d, c->d) || !same_launch(c->graph_cfg, c->cfg) || c->graph_nwk != c->n_wk) {
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    for (auto &g : c->graph)
+      if (g) {
+        HIP_TRY(hipGraphExecDestroy(g));
+        g = nullptr;
+      }
+    c->graph_d = c->d;
+    c->graph_cfg = c->cfg;
+    c->graph_nwk = c->n_wk;
+  }
+  if (!c->graph[c->cur])
+    if (hlb_status st = capture_steps(c, c->cur)) return st;
+  HIP_TRY(launch_set_time(c->t_dev, c->t, c->stream));
+  for (int64_t r = 0; r < reps; ++r) HIP_TRY(hipGraphLaunch(c->graph[c->cur], c->stream));
+  // an even number of steps per graph: the state is back in buffer cur
+  c->direct = false;
+  c->t += reps * c->graph_steps;
+  return HLB_OK;
+}
+
+}  // namespace
+
 hlb_status hlb_step(hlb_ctx *c, int64_t n) {
   if (hlb_status st = check_ctx(c)) return st;
   if (n < 0) return fail(HLB_EINVAL, "n < 0");
   if (c->split_pending) return fail(HLB_ESTATE, "a split step is in progress (hlb_step_mid is due)");
   if (hlb_status st = bind(c)) return st;
+  if (c->graph_steps > 0 && !c->timing && n >= c->graph_steps) {
+    const int64_t reps = n / c->graph_steps;
+    if (hlb_status st = replay_steps(c, reps)) return st;
+    n -= reps * c->graph_steps;
+  }
   for (int64_t s = 0; s < n; ++s) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (c->timing) {
@@ -1120,6 +1217,8 @@ hlb_status hlb_info(const hlb_ctx *c, hlb_info_t *info) {
   info->adjoint = c->adj_on ? 1 : 0;
   info->porous = c->cfg.porous ? 1 : 0;
   info->scheme = c->cfg.scheme;
+  info->sites_per_thread = c->cfg.sites_per_thread;
+  info->graph_steps = c->graph_steps;
   info->device_bytes = c->dev_bytes;
   return HLB_OK;
 }

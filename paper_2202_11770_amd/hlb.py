@@ -48,7 +48,8 @@ class hlb_iolet(ctypes.Structure):
 class hlb_options(ctypes.Structure):
     _fields_ = [("storage", ctypes.c_int32), ("order", ctypes.c_int32), ("xcd_remap", ctypes.c_int32),
                 ("adjoint", ctypes.c_int32), ("rho0", ctypes.c_double), ("max_device_bytes", ctypes.c_int64),
-                ("scheme", ctypes.c_int32), ("sites_per_thread", ctypes.c_int32)]
+                ("scheme", ctypes.c_int32), ("sites_per_thread", ctypes.c_int32),
+                ("graph_steps", ctypes.c_int32)]
 
 
 class hlb_windkessel(ctypes.Structure):
@@ -61,7 +62,8 @@ class hlb_info_t(ctypes.Structure):
                 ("storage", ctypes.c_int32), ("order", ctypes.c_int32), ("bytes_per_lup", ctypes.c_double),
                 ("device_bytes", ctypes.c_int64), ("table_bytes_per_site", ctypes.c_double),
                 ("n_segments", ctypes.c_int64), ("n_iolets", ctypes.c_int64), ("adjoint", ctypes.c_int32),
-                ("porous", ctypes.c_int32), ("scheme", ctypes.c_int32)]
+                ("porous", ctypes.c_int32), ("scheme", ctypes.c_int32), ("sites_per_thread", ctypes.c_int32),
+                ("graph_steps", ctypes.c_int32)]
 
 
 class hlb_stats_t(ctypes.Structure):
@@ -307,7 +309,8 @@ def hlb_info(ctx) -> dict:
     return dict(n_sites=i.n_sites, n_padded=i.n_padded, group_sites=list(i.group_sites), storage=i.storage,
                 order=i.order, bytes_per_lup=i.bytes_per_lup, device_bytes=i.device_bytes,
                 table_bytes_per_site=i.table_bytes_per_site, n_segments=i.n_segments, n_iolets=i.n_iolets,
-                adjoint=i.adjoint, porous=i.porous, scheme=i.scheme)
+                adjoint=i.adjoint, porous=i.porous, scheme=i.scheme, sites_per_thread=i.sites_per_thread,
+                graph_steps=i.graph_steps)
 
 
 def hlb_macros(ctx, want=("rho", "u", "wss")):
@@ -443,10 +446,11 @@ class Simulation:
     @classmethod
     def create(cls, geom, tau: float, storage: str = "f64", order: str = "lex", xcd_remap: int = 8,
                rho0: float = 1.0, max_device_bytes: int = 0, tables=None, adjoint: bool = False,
-               scheme: str = "pull", sites_per_thread: int = 0):
+               scheme: str = "pull", sites_per_thread: int = 0, graph_steps: int = 0):
         opt = hlb_default_options()
         opt.scheme = SCHEME[scheme]
         opt.sites_per_thread = int(sites_per_thread)
+        opt.graph_steps = int(graph_steps)
         opt.storage = STORAGE[storage]
         opt.order = ORDER[order]
         opt.xcd_remap = int(xcd_remap)

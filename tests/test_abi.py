@@ -36,7 +36,7 @@ def test_exports_every_declared_symbol():
 def test_default_options():
     o = hlb.hlb_default_options()
     assert (o.storage, o.order, o.xcd_remap, o.adjoint, o.rho0, o.max_device_bytes) == (0, 1, 8, 0, 1.0, 0)
-    assert (o.scheme, o.sites_per_thread) == (hlb.HLB_SCHEME_PULL, 0)
+    assert (o.scheme, o.sites_per_thread, o.graph_steps) == (hlb.HLB_SCHEME_PULL, 0, 0)
 
 
 @pytest.fixture(scope="module")
@@ -117,6 +117,11 @@ def test_rejects_bad_options(cyl):
     o.adjoint = 1
     o.storage = hlb.HLB_F32_SHIFTED
     _expect(hlb.HLB_EINVAL, hlb.hlb_create, cyl.coords, cyl.types, cyl.nbr, 0.8, cyl.iolets, o, match="FP64")
+    for bad in (-1, 3, 4098):
+        o = hlb.hlb_default_options()
+        o.graph_steps = bad
+        _expect(hlb.HLB_EINVAL, hlb.hlb_create, cyl.coords, cyl.types, cyl.nbr, 0.8, cyl.iolets, o,
+                match="graph_steps")
     for bad in (-1, 3):
         o = hlb.hlb_default_options()
         o.sites_per_thread = bad
