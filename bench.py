@@ -293,13 +293,18 @@ def run_adjoint(g, tables, tau, n=40, n_snap=10):
     J, _, _, fw = hlb.hlb_adjoint_run(sim.ctx, n, n // 2, n, n_snap)
     wall = time.perf_counter() - t0
     st = hlb.hlb_stats(sim.ctx)
+    # the forward step kernel in the same context (its site order)
+    hlb.hlb_set_timing(sim.ctx, True)
+    sim.step(20)
+    fwd_ms = hlb.hlb_stats(sim.ctx)["kernel_ms"]
     sim.close()
     bps = 5 * 19 * 8 + 2 * info["table_bytes_per_site"] + 16 + 4 + 4
     gbs = bps * info["n_sites"] / (st["adj_ms"] * 1e-3) / 1e9
     return {"steps": n, "snapshots": n_snap, "forward_steps": fw, "wall_s": round(wall, 3),
             "reverse_step_ms": round(st["adj_ms"], 4), "bytes_per_site": round(bps, 2),
             "achieved_gbs": round(gbs, 1), "frac": round(gbs / PEAK_GBS, 4),
-            "reverse_mlups": round(info["n_sites"] / st["adj_ms"] / 1e3, 1), "J": J}
+            "reverse_mlups": round(info["n_sites"] / st["adj_ms"] / 1e3, 1),
+            "forward_step_ms": round(fwd_ms, 4), "J": J}
 
 
 def copy_ceiling(nbytes=4 << 30, reps=20):
