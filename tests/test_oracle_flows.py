@@ -11,7 +11,8 @@ Every check here is fixed by something other than the oracle's code:
 * plane Couette flow between a bounce-back wall and a Ladd velocity lid:
   exact linear profile (pins the sign and factor of the Ladd term);
 * pressure-driven square duct: textbook Fourier-series profile (pins the
-  ghost-density pressure iolet and eq. (8));
+  ghost-density pressure iolet and eq. (8)), converging at second order
+  when the cross-section doubles;
 * the straight-pipe configuration: Poiseuille profile, pressure drop, flux
   and wall shear stress (pins the wall shear stress definition's scale);
 * porous walls: a box whose walls all leak to the reservoir reaches the
@@ -192,6 +193,32 @@ def test_duct_pressure_poiseuille(orc, tau, steps):
     P2.run(f2, 0, 300)
     _, u2, _ = P2.macros(f2)
     assert np.abs(u2).max() <= 1e-15
+
+
+def test_duct_second_order_convergence(orc):
+    """Doubling the duct's cross-section (8x8 -> 16x16, length with it, the
+    run long enough to converge in both) cuts the profile error against the
+    series about fourfold: second-order accuracy of the bulk scheme with
+    mid-link bounce-back and the ghost-density iolets at fixed tau."""
+    tau = 0.8
+    nu = (tau - 0.5) / 3.0
+    errs = []
+    for w, L, steps in ((8, 32, 2000), (16, 64, 8000)):
+        g = G.duct(w, w, L, rho_in=1.006, rho_out=1.0)
+        P = orc.Problem(g, tau)
+        f = P.init()
+        P.run(f, 0, steps)
+        rho, u, _ = P.macros(f)
+        x, y, z = (g.coords[:, a] for a in range(3))
+        zs = np.arange(L // 4, 3 * L // 4)
+        Gp = -np.polyfit(zs, np.array([rho[z == k].mean() for k in zs]), 1)[0] / 3.0
+        mid = z == L // 2
+        c = (w - 1) / 2
+        exact = _duct_series(x[mid] - c, y[mid] - c, w / 2, w / 2, Gp, rho[mid].mean() * nu)
+        errs.append(np.linalg.norm(u[mid, 2] - exact) / np.linalg.norm(exact))
+    print(f"L2 errors {errs[0]:.3e} (8x8), {errs[1]:.3e} (16x16), ratio {errs[0] / errs[1]:.2f}")
+    assert errs[1] <= 0.005
+    assert errs[0] / errs[1] >= 3.0
 
 
 def test_cylinder_poiseuille(orc):
