@@ -76,6 +76,40 @@ __device__ inline T *at(T *A, int32_t q, int i) {
   }
 }
 
+// Cheaper addressing for the bulk+wall path of the step kernel when a buffer
+// is at most 4 GiB.  Byte offset of (q, d) in a tiled buffer:
+//   sz q + (q >> 12) KT + d D,   D = 4096 sz (one direction run of a tile),
+//   KT = 18 D (the other runs of a tile).
+// The direction term goes into a per-direction base held in scalar
+// registers, dir_base(A, d) = A + d D - BIAS, and each lane supplies
+//   voff(jb) = (jb >> (12 + log2 sz)) KT + jb,  jb = sz q + D,
+// which equals sz q + (q >> 12) KT + BIAS (adding D = 2^(12 + log2 sz) to
+// sz q adds exactly one to the tile number): one shift and one 24-bit
+// multiply-add per address.  BIAS = KT + D keeps every lane offset
+// non-negative, the reflected slot of a wall link included:
+//   (p, opp(i)) = dir_base(A, i) + voff(sz p + D) + (opp(i) - i) D.
+template <typename T>
+struct Narrow {
+  static constexpr uint32_t S = sizeof(T) == 8 ? 3u : (sizeof(T) == 4 ? 2u : 1u);
+  static constexpr uint32_t D = uint32_t(kPopTile) * uint32_t(sizeof(T));
+  static constexpr uint32_t KT = uint32_t(Q - 1) * D;
+  static constexpr uint32_t BIAS = KT + D;
+  static_assert(KT < (1u << 24), "24-bit multiply-add");
+  __device__ static uint32_t voff(uint32_t jb) {
+    return (jb >> (kPopTileShift + S)) * KT + jb;
+  }
+  // The empty asm keeps the compiler from folding the base's constant into
+  // the lane offset (which would need 64-bit lane arithmetic): the load then
+  // takes the scalar base plus the 32-bit lane offset.
+  template <typename P>
+  __device__ static P *at(P *A, int d, uint32_t off) {
+    using GB = __attribute__((address_space(1))) char;
+    GB *base = (GB *)A + (int64_t(d) * D - int64_t(BIAS));
+    asm("" : "+s"(base));
+    return (P *)(base + off);
+  }
+};
+
 __device__ inline double ld(const double *p) { return *p; }
 __device__ inline float ld(const float *p) { return *p; }
 __device__ inline float ld(const _Float16 *p) { return static_cast<float>(*p); }
@@ -218,7 +252,7 @@ static_assert(kSegRow == 20, "segment rows are five 16-byte vectors");
 
 // Source offsets of the 18 incoming links of bulk+wall position p, whose
 // kSegBlock-position block is blk: off[i-1] = source - p, the source being
-// a fluid position in [0, np), or for a wall link an offset of +-np that
+// a fluid position in [0, np), or for a wall link the offset np, which
 // leaves [0, np) (the link then reads the site's own direction opp(i)).
 __device__ inline void bulk_offsets(const GatherArgs &a, int64_t p, int64_t blk, int32_t (&off)[Q - 1]) {
   const int32_t s = a.seg_base[blk] + (int32_t)ld_stream(a.seg_delta + p);
@@ -257,7 +291,38 @@ __device__ inline C gather(const T *__restrict__ A, int64_t p, int64_t blk, cons
                            WkFlux *wkf = nullptr) {
   const int64_t np = a.np;
   C flux = 0;
-  if constexpr (!IOLET) {
+  if constexpr (!IOLET && NARROW) {
+    // Bulk+wall group, buffers of at most 4 GiB (see Narrow).  A wall link's
+    // offset np puts jb at or above sz np + D.
+    using N = Narrow<T>;
+    int32_t off[Q - 1];
+    bulk_offsets(a, p, blk, off);
+    // The empty asm statements keep pb whole (so that each jb is one
+    // shift-and-add) and make every lane compute its neighbour's offset (so
+    // that the wall choice stays a select instead of a branch).
+    uint32_t pb = ((uint32_t)p << N::S) + N::D;
+    asm("" : "+v"(pb));
+    const uint32_t own = N::voff(pb);
+    const uint32_t wall_lo = own - N::D, wall_hi = own + N::D;  // (p, opp(i)) for even / odd i
+    const uint32_t jb_wall = ((uint32_t)np << N::S) + N::D;
+    g[0] = ld(N::at(A, 0, own));
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+      const uint32_t jb = ((uint32_t)off[i - 1] << N::S) + pb;
+      uint32_t vj = N::voff(jb);
+      asm("" : "+v"(vj));
+      const bool wall = jb >= jb_wall;
+      C v = ld(N::at(A, i, wall ? (opp(i) > i ? wall_hi : wall_lo) : vj));
+      if constexpr (POROUS) {
+        if (wall) {
+          const C nv = v - C(a.phi[p]) * (v - rest<SH, C>(i, C(a.rho0)));
+          flux += nv - v;
+          v = nv;
+        }
+      }
+      g[i] = v;
+    }
+  } else if constexpr (!IOLET) {
     // Bulk+wall group: every link, bounce-back included, is one load; the
     // offsets are fetched before the 18 gathers are issued.
     int32_t off[Q - 1];

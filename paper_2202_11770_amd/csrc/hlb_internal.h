@@ -18,8 +18,9 @@ constexpr int kGroups = 5;
 constexpr int64_t kGroupAlign = 256;
 // Bulk+wall group pull table: positions [0, n0) are cut into segments of
 // consecutive positions whose 18 incoming links have the same source offsets
-// (source position minus own position; a wall link's offset is
-// (opp(i) - i) np, which lands on the site's own slot of direction opp(i)).
+// (source position minus own position; a wall link's offset is np, which
+// puts the source outside [0, np): the link then reads the site's own slot
+// of direction opp(i)).
 // Each segment stores its offsets once, as a row of kSegRow int32 (18 used,
 // padded for 16-byte loads); each position stores a one-byte segment index
 // relative to the first segment of its kSegBlock-position block.

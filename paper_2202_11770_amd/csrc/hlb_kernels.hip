@@ -83,8 +83,15 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kStepWav
       C g[Q];
       flux = gather<false, POROUS, SH, NARROW>(A, p, blk, a, g);
       collide<SH>(g, omega, C(a.rho0));
+      if constexpr (NARROW) {
+        using N = Narrow<T>;
+        const uint32_t own = N::voff(((uint32_t)p << N::S) + N::D);
 #pragma unroll
-      for (int i = 0; i < Q; ++i) st(at<NARROW>(B, (int32_t)p, i), g[i]);
+        for (int i = 0; i < Q; ++i) st(N::at(B, i, own), g[i]);
+      } else {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) st(at<NARROW>(B, (int32_t)p, i), g[i]);
+      }
     }
     if constexpr (POROUS) {
       const double s = wave_sum(double(flux));
@@ -389,8 +396,10 @@ hipError_t step_impl(const LaunchCfg &cfg, const Layout &L, const DevPtrs &d, in
   const unsigned grid = (unsigned)(nb_io + nb_launch);
   hipError_t er;
   if (e0 && (er = hipEventRecord(e0, s)) != hipSuccess) return er;
-  // byte offsets fit in 32 bits when a whole population buffer does
-  const bool narrow = kStepNarrow<T> && (uint64_t)Q * (uint64_t)L.np * sizeof(T) <= (uint64_t(1) << 32);
+  // byte offsets fit in 32 bits when a whole population buffer does, with
+  // the bias of the bulk path's addressing (Narrow)
+  const bool narrow = kStepNarrow<T> && (uint64_t)Q * (uint64_t)L.np * sizeof(T) + Narrow<T>::BIAS <=
+                                            (uint64_t(1) << 32);
   if (grid > 0) {
 #define HLB_STEP(P, N)                                                                                    \
   do {                                                                                                  \

@@ -572,7 +572,7 @@ static hlb_status create_impl(int64_t n, const int32_t *coords, const uint8_t *t
   const int64_t nb0 = (n0 + kSegBlock - 1) / kSegBlock;
   auto offset_of = [&](int64_t p, int i) -> int32_t {
     const int32_t y = nbr[Q * (int64_t)c->order_host[p] + OPP(i)];
-    return y >= 0 ? (int32_t)(inv[y] - p) : (int32_t)((int64_t)(OPP(i) - i) * np);
+    return y >= 0 ? (int32_t)(inv[y] - p) : (int32_t)np;
   };
   std::vector<int32_t> segid(n0);
 #pragma omp parallel for schedule(static)
