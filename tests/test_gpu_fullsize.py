@@ -1,8 +1,10 @@
 """Parity at the benchmark's full size and launch configuration.
 
 The 2.0e7-site tree of the benchmark (seed 2, 8 generations, tau 0.6, one
-Ladd inlet, 256 pressure outlets), default order and launch, FP64: a few steps
-from the inlet-amplitude peak, every site compared against the oracle.
+Ladd inlet, 256 pressure outlets), default order and launch, every storage: a
+few steps from the inlet-amplitude peak, every site compared against the
+oracle; and the adjoint in the benchmark's configuration against central
+differences of the GPU objective.
 """
 import sys
 import time
@@ -27,26 +29,36 @@ def tree20m():
     return g, tables
 
 
-def test_tree_20m_fp64_parity(tree20m):
+def test_tree_20m_parity(tree20m):
+    """Every storage against one oracle run; bars as in the smaller cases
+    (FP64 1e-12; FP32 1e-5; FP16 the stated storage bound)."""
     g, tables = tree20m
     t0, steps, tau = 1000, 6, 0.6  # start at the inlet amplitude's peak
-    print(f"case: tree {g.n} sites, t0 {t0}, {steps} steps, f64, default launch", flush=True)
-    sim = hlb.Simulation.create(g, tau, tables=tables)
-    hlb.hlb_init_equilibrium(sim.ctx, None, None, t0)
-    sim.step(steps)
-    rho, u, wss = sim.macros()
-    m, r = hlb.hlb_mass_balance(sim.ctx)
-    sim.close()
     P = oracle.Problem(g, tau, tables=tables)
     f = P.init()
     t = time.time()
     P.run(f, t0, steps)
     print(f"oracle {steps} steps in {time.time() - t:.1f}s", flush=True)
-    e = errors(rho, u, wss, *P.macros(f))
-    print("tree20m f64:", fmt(e), flush=True)
-    assert e["e_rho"] <= 1e-12 and e["e_u"] <= 1e-12 and e["e_wss"] <= 1e-10
-    assert abs(m - P.mass(f)) / m <= 1e-12
-    assert abs(r) / m <= steps * 19 * 2.0 ** -53 / tau
+    ref = P.macros(f)
+    m_ref = P.mass(f)
+    for st in ("f64", "f32", "f16"):
+        print(f"case: tree {g.n} sites, t0 {t0}, {steps} steps, {st}, default launch", flush=True)
+        sim = hlb.Simulation.create(g, tau, storage=st, tables=tables)
+        hlb.hlb_init_equilibrium(sim.ctx, None, None, t0)
+        sim.step(steps)
+        rho, u, wss = sim.macros()
+        m, r = hlb.hlb_mass_balance(sim.ctx)
+        sim.close()
+        e = errors(rho, u, wss, *ref)
+        print(f"tree20m {st}:", fmt(e), flush=True)
+        if st == "f64":
+            assert e["e_rho"] <= 1e-12 and e["e_u"] <= 1e-12 and e["e_wss"] <= 1e-10
+            assert abs(m - m_ref) / m <= 1e-12
+            assert abs(r) / m <= steps * 19 * 2.0 ** -53 / tau
+        elif st == "f32":
+            assert e["e_rho"] <= 1e-5 and e["e_u"] <= 1e-5 and e["e_wss"] <= 1e-3
+        else:
+            assert e["e_rho"] <= 1e-2 and e["e_u"] <= 0.2
 
 
 def test_tree_20m_adjoint_vs_finite_differences(tree20m):
