@@ -265,8 +265,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) 
   wave_add_grouped(A.dA + A.step, dtab, A.n_steps);  // one atomic per iolet per wavefront
 }
 
-// mu_{t-1} = (dG_t/ds_{t-1})^T nu_t (compiled for 4 waves per SIMD, no
-// spills; the default allocation gave 3): population i of p at t-1 went to the
+// mu_{t-1} = (dG_t/ds_{t-1})^T nu_t (compiled for 4 waves per SIMD; only the
+// iolet path spills, and the default allocation gave 3): population i of p at t-1 went to the
 // site at x + c_i -- the pull entry of direction opp(i), which names the
 // site that pulled it --, was reflected back to p (wall: times 1 - phi;
 // Ladd: plus a constant), or was replaced (pressure iolet: no direct path,
