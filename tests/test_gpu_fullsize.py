@@ -105,3 +105,31 @@ def test_tree_20m_adjoint_vs_finite_differences(tree20m):
     print(f"J {J:.10e}; amplitudes: adjoint {ad:.10e} FD {fd:.10e} rel {e_amp:.1e}; "
           f"porosity: adjoint {adp:.10e} FD {fdp:.10e} rel {e_phi:.1e}", flush=True)
     assert e_amp <= 1e-6 and e_phi <= 1e-6
+
+
+def test_tree_30m_fp64_wide_addressing_parity():
+    """Above 4 GiB per population buffer the step kernel forms 64-bit
+    addresses instead of 32-bit offsets from a scalar base.  A 3.0e7-site
+    tree in FP64 (4.6 GB per buffer) takes that path; every site is
+    compared against the oracle after a few steps from the inlet peak."""
+    sys.path.insert(0, ".")
+    import bench
+    t = time.time()
+    g, tables = bench.tree_workload(target=30_000_000)
+    print(f"tree {g.n} sites generated in {time.time() - t:.1f}s", flush=True)
+    t0, steps, tau = 1000, 4, 0.6
+    sim = hlb.Simulation.create(g, tau, tables=tables)
+    info = hlb.hlb_info(sim.ctx)
+    assert 19 * info["n_padded"] * 8 > 2 ** 32, "the case must exceed 4 GiB per buffer"
+    print(f"case: tree {g.n} sites ({19 * info['n_padded'] * 8 / 1e9:.2f} GB per buffer), t0 {t0}, {steps} steps, f64",
+          flush=True)
+    hlb.hlb_init_equilibrium(sim.ctx, None, None, t0)
+    sim.step(steps)
+    rho, u, wss = sim.macros()
+    sim.close()
+    P = oracle.Problem(g, tau, tables=tables)
+    f = P.init()
+    P.run(f, t0, steps)
+    e = errors(rho, u, wss, *P.macros(f))
+    print("tree30m f64:", fmt(e), flush=True)
+    assert e["e_rho"] <= 1e-12 and e["e_u"] <= 1e-12 and e["e_wss"] <= 1e-10
