@@ -133,3 +133,32 @@ def test_tree_30m_fp64_wide_addressing_parity():
     e = errors(rho, u, wss, *P.macros(f))
     print("tree30m f64:", fmt(e), flush=True)
     assert e["e_rho"] <= 1e-12 and e["e_u"] <= 1e-12 and e["e_wss"] <= 1e-10
+
+
+def test_tree_120m_fp16_wide_addressing_parity():
+    """The same for FP16 storage, which crosses 4 GiB per buffer only above
+    1.13e8 sites: a 1.2e8-site tree, against the oracle at every site, to
+    the FP16 storage bound."""
+    sys.path.insert(0, ".")
+    import bench
+    t = time.time()
+    g, tables = bench.tree_workload(target=120_000_000)
+    print(f"tree {g.n} sites generated in {time.time() - t:.1f}s", flush=True)
+    t0, steps, tau = 1000, 4, 0.6
+    sim = hlb.Simulation.create(g, tau, storage="f16", tables=tables)
+    info = hlb.hlb_info(sim.ctx)
+    assert 19 * info["n_padded"] * 2 > 2 ** 32, "the case must exceed 4 GiB per buffer"
+    print(f"case: tree {g.n} sites ({19 * info['n_padded'] * 2 / 1e9:.2f} GB per buffer), t0 {t0}, {steps} steps, f16",
+          flush=True)
+    hlb.hlb_init_equilibrium(sim.ctx, None, None, t0)
+    sim.step(steps)
+    rho, u, wss = sim.macros()
+    sim.close()
+    P = oracle.Problem(g, tau, tables=tables)
+    f = P.init()
+    t = time.time()
+    P.run(f, t0, steps)
+    print(f"oracle {steps} steps in {time.time() - t:.1f}s", flush=True)
+    e = errors(rho, u, wss, *P.macros(f))
+    print("tree120m f16:", fmt(e), flush=True)
+    assert e["e_rho"] <= 1e-2 and e["e_u"] <= 0.2
