@@ -162,3 +162,29 @@ def test_tree_120m_fp16_wide_addressing_parity():
     e = errors(rho, u, wss, *P.macros(f))
     print("tree120m f16:", fmt(e), flush=True)
     assert e["e_rho"] <= 1e-2 and e["e_u"] <= 0.2
+
+
+def test_tree_200m_fp64_parity():
+    """The 2.0e8-site tree of the large workload (30 GB per FP64 buffer),
+    default launch: every site against the oracle after a few steps from the
+    inlet peak (the oracle needs about 80 GB of host memory here)."""
+    sys.path.insert(0, ".")
+    import bench
+    t = time.time()
+    g, tables = bench.workload("tree200m")
+    print(f"tree {g.n} sites generated in {time.time() - t:.1f}s", flush=True)
+    t0, steps, tau = 1000, 3, 0.6
+    print(f"case: tree {g.n} sites, t0 {t0}, {steps} steps, f64", flush=True)
+    sim = hlb.Simulation.create(g, tau, tables=tables)
+    hlb.hlb_init_equilibrium(sim.ctx, None, None, t0)
+    sim.step(steps)
+    rho, u, wss = sim.macros()
+    sim.close()
+    P = oracle.Problem(g, tau, tables=tables)
+    f = P.init()
+    t = time.time()
+    P.run(f, t0, steps)
+    print(f"oracle {steps} steps in {time.time() - t:.1f}s", flush=True)
+    e = errors(rho, u, wss, *P.macros(f))
+    print("tree200m f64:", fmt(e), flush=True)
+    assert e["e_rho"] <= 1e-12 and e["e_u"] <= 1e-12 and e["e_wss"] <= 1e-10
