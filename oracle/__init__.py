@@ -1,7 +1,7 @@
 """FP64 CPU oracle of the sparse D3Q19 LBGK update -- TEST INFRASTRUCTURE ONLY.
 
-Only the test suite, the smoke check and the benchmark's CPU-baseline leg may
-import this package.  It shares no code with the GPU library; the only thing
+Only the test suite, the smoke check and the benchmark's CPU legs (the CPU
+baseline and the oracle timing table) may import this package.  It shares no code with the GPU library; the only thing
 both consume is the geometry produced by the seeded input generators.
 
 Thin ctypes marshalling over ``oracle.c`` (plain C, FP64, array-of-structures,

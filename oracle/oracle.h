@@ -2,8 +2,8 @@
  * oracle.h -- plain FP64 CPU reference of the sparse D3Q19 LBGK update.
  *
  * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may include, link
- * or call this code; only the test suite, the smoke check and the CPU
- * baseline leg of the benchmark use it.  It shares no code, header, table or
+ * or call this code; only the test suite, the smoke check and the CPU legs
+ * of the benchmark (baseline, timing table) use it.  It shares no code, header, table or
  * constant with the GPU library.
  *
  * What it computes (Zacharoudiou, McCullough, Coveney, "Development and

@@ -54,7 +54,7 @@ def test_capacitor_integrates_outflow():
     C, X0 = 500.0, 0.001
     P = oracle.Problem(g, 0.8)
     f = P.init()
-    # outflows step by step, from the same driver one step at a time
+    # outflows step by step, from the same routine run one step at a time
     Qs = []
     for s in range(100):
         st = P.run_windkessel(f, s, 1, {k: (1.0, 0.0, C, 0.0, X0 + sum(Qs) / C)})
