@@ -12,11 +12,11 @@
  *   - mid-link bounce-back at walls                            (Sec. 2.3.1)
  *   - velocity iolets by Ladd's corrected bounce-back and pressure iolets by
  *     a ghost density                                          (Sec. 2.3.2)
- *   - sites grouped by collision-streaming type, one wavefront-uniform
- *     kernel per group, structure-of-arrays populations, f_old / f_new
- *     swapped by pointer each step                             (Sec. 3.2.2-3.2.3)
+ *   - sites grouped by collision-streaming type, a wavefront-uniform code
+ *     path per group, structure-of-arrays populations (per tile of 4096
+ *     sites), f_old / f_new swapped by pointer each step     (Sec. 3.2.2-3.2.3)
  * computed on the GPU as a pull (gather-then-collide) update over a sparse
- * list of fluid sites ordered along a space-filling curve.
+ * list of fluid sites, lexicographic within each group by default.
  *
  * Conventions (every function):
  *   - returns hlb_status: HLB_OK (0) or a negative error code; the text of

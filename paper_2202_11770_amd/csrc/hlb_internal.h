@@ -130,8 +130,8 @@ hipError_t launch_set_state(const LaunchCfg &cfg, const Layout &L, const DevPtrs
                             const double *staging, hipStream_t s);
 // Device buffers of the adjoint sweep (FP64 storage only).
 struct AdjBuffers {
-  double *mu = nullptr;       // [19][np] adjoint of the post-collision state
-  double *nu = nullptr;       // [19][np] adjoint of the pre-collision state
+  double *mu = nullptr;       // adjoint of the post-collision state (tiled, as the state)
+  double *nu = nullptr;       // adjoint of the pre-collision state (tiled, as the state)
   double *J = nullptr;        // objective accumulator
   double *dA = nullptr;       // [n_iolets][n_steps]
   double *dphi = nullptr;     // [np] porosity derivative per position

@@ -1,10 +1,10 @@
 // gfx950 kernels of the sparse D3Q19 LBGK update (pull scheme).
 //
-// One thread owns one fluid site.  Populations live in two structure-of-
-// arrays buffers (Sec. 3.2.3: SoA on the GPU; f_old / f_new swapped by
-// pointer), each [19][np] of the storage type.  FP64 stores f_i itself, as
-// the paper does; the FP32 / FP16 forms store the deviation f_i - w_i rho0
-// from the rest state and collide in FP32.  A step gathers the 19
+// One thread owns one fluid site.  Populations live in two buffers (f_old /
+// f_new swapped by pointer, Sec. 3.2.3), each a structure of arrays per
+// tile of 4096 positions, [np/4096][19][4096] of the storage type.  FP64
+// stores f_i itself, as the paper does; the FP32 / FP16 forms store the
+// deviation f_i - w_i rho0 from the rest state and collide in FP32.  A step gathers the 19
 // post-collision populations that stream into the site (eq. (3b) read
 // backwards: the pull order the paper proposes in its future-work section),
 // substitutes the boundary rules for links that cross a wall or an iolet
@@ -13,7 +13,7 @@
 //
 // Sites are grouped by collision-streaming type (Sec. 3.2.2): positions
 // [0, n0) hold the merged bulk+wall group, whose pull table encodes
-// bounce-back as a plain indexed load; the four iolet groups follow, each
+// bounce-back as one load with a selected address; the four iolet groups follow, each
 // starting on a 256-site boundary, with the boundary rules applied per link.
 // k_step runs both code paths in one launch, one group per workgroup.
 //
