@@ -360,13 +360,22 @@ hlb_status hlb_set_objective(hlb_ctx *ctx, int32_t kind, const double *weights);
  *           porosity (hlb_set_porosity), zero at sites without wall links,
  *           evaluated at the current porosity (0 if none is set).
  * The forward states are recomputed from n_snap device snapshots
- * (1 <= n_snap <= 4096; binomial checkpointing after Griewank & Walther's
- * revolve): with n <= C(n_snap - 1 + r, r) the forward sweep is repeated at
- * most r times.  *forward_steps (may be NULL) receives the forward steps
- * run.  The state is left as it was (time t0).  Needs opt.adjoint at
- * creation and FP64 storage (HLB_ESTATE otherwise). */
+ * (1 <= n_snap <= 4096, the start state's included; binomial checkpointing
+ * after Griewank & Walther): the schedule takes the fewest forward steps
+ * possible with n_snap slots, r n - C(n_snap + r, r - 1) with r the least
+ * integer with C(n_snap + r, n_snap) >= n (hlb_revolve_forward_steps).
+ * *forward_steps (may be NULL) receives the forward steps run.  The state
+ * is left as it was (time t0).  Needs opt.adjoint at creation and FP64
+ * storage (HLB_ESTATE otherwise). */
 hlb_status hlb_adjoint_run(hlb_ctx *ctx, int64_t n, int64_t obj_t0, int64_t obj_t1, int32_t n_snap,
                            double *J, double *dJ_dA, double *dJ_dphi, int64_t *forward_steps);
+
+/* Forward steps hlb_adjoint_run takes for n >= 1 steps with n_snap
+ * snapshots (1 <= n_snap <= 4096), without running anything: for planning
+ * snapshot memory (n_snap state buffers) against recomputation.  Host-only;
+ * needs no context or device.  Errors: HLB_EINVAL (arguments out of range,
+ * steps NULL). */
+hlb_status hlb_revolve_forward_steps(int64_t n, int32_t n_snap, int64_t *steps);
 
 /* Device snapshots of the whole state (for checkpointing schedules).
  * hlb_snapshot_alloc reserves n_slots slots (frees previous ones). */

@@ -1384,21 +1384,65 @@ namespace {
 int64_t binom_sat(int64_t n, int64_t k) {
   if (k < 0 || k > n) return 0;
   if (k > n - k) k = n - k;
-  long double v = 1.0L;
+  // v = C(n - k + i, i) after step i: exact in integers, saturated at 2^62
+  __int128 v = 1;
   for (int64_t i = 1; i <= k; ++i) {
-    v = v * (long double)(n - k + i) / (long double)i;
-    if (v > 4.6e18L) return (int64_t)1 << 62;
+    v = v * (n - k + i) / i;
+    if (v > ((__int128)1 << 62)) return (int64_t)1 << 62;
   }
-  return (int64_t)(v + 0.5L);
+  return (int64_t)v;
 }
 
-// Reverse sweep with binomial checkpointing (Griewank & Walther's revolve
-// schedule, written as a recursion): the state at time a is in slot
-// `slot_a`, `cfree` more slots are free; adjoint steps b, b-1, ..., a+1 are
-// run, each with the forward state of the preceding time restored or
-// recomputed.  With l = b - a steps and r the least integer with
-// C(cfree + r, cfree) >= l, a checkpoint is placed so that the part after it
-// fits C(cfree - 1 + r, cfree - 1) steps.
+// Forward steps of the cheapest reversal of l steps with S checkpoint slots,
+// the one holding the start state included (Griewank & Walther, binomial
+// checkpointing): with r the least integer with C(S + r, S) >= l, it is
+// r l - C(S + r, r - 1); l (l - 1) / 2 with the start state alone.
+int64_t revolve_cost(int64_t l, int64_t S) {
+  if (l <= 1) return 0;
+  if (S <= 1) return l * (l - 1) / 2;
+  int64_t r = 0;
+  while (binom_sat(S + r, S) < l) ++r;
+  return r * l - binom_sat(S + r, r - 1);
+}
+
+// Where to place the next checkpoint when l > 1 steps remain with S slots
+// (S >= 2): m steps ahead, m in [1, l - 1] minimising
+//   m + revolve_cost(l - m, S - 1) + revolve_cost(m, S)
+// -- reach the checkpoint, reverse the part after it with one slot less,
+// then the part before it with the slot freed again.  The sum is convex in
+// m (each term is piecewise linear with growing slopes), so a bisection on
+// its forward difference finds the minimum, and the recursion meets
+// revolve_cost(l, S) exactly.
+int64_t revolve_split(int64_t l, int64_t S) {
+  auto cost = [&](int64_t m) { return m + revolve_cost(l - m, S - 1) + revolve_cost(m, S); };
+  int64_t lo = 1, hi = l - 1;
+  while (lo < hi) {
+    const int64_t mid = lo + (hi - lo) / 2;
+    if (cost(mid + 1) >= cost(mid)) hi = mid;
+    else lo = mid + 1;
+  }
+  return lo;
+}
+
+// Forward steps the reverse sweep of Revolve takes from a to b with cfree
+// free slots (a dry run of its recursion).
+int64_t revolve_forward_steps(int64_t a, int64_t b, int64_t cfree) {
+  int64_t fwd = 0;
+  while (b - a > 1 && cfree > 0) {
+    const int64_t m = a + revolve_split(b - a, cfree + 1);
+    fwd += m - a + revolve_forward_steps(m, b, cfree - 1);
+    b = m;
+  }
+  return fwd + (b - a) * (b - a - 1) / 2;  // each step recomputed from a
+}
+
+// Reverse sweep with binomial checkpointing (Griewank & Walther's schedule,
+// written as a recursion): the state at time a is in slot `slot_a`, `cfree`
+// more slots are free; adjoint steps b, b-1, ..., a+1 are run, each with
+// the forward state of the preceding time restored or recomputed.  While
+// slots are free, a checkpoint is placed revolve_split() steps ahead and
+// the part after it is reversed first; with none free, each step is
+// recomputed from a.  The forward steps total revolve_cost(n, n_snap).
 struct Revolve {
   hlb_ctx *c;
   int64_t t0, n, w0, w1, n_snap;
@@ -1466,11 +1510,7 @@ struct Revolve {
   }
   hlb_status reverse(int64_t a, int64_t b, int64_t slot_a, int64_t cfree) {
     while (b - a > 1 && cfree > 0) {
-      const int64_t l = b - a;
-      int64_t r = 1;
-      while (binom_sat(cfree + r, cfree) < l) ++r;
-      const int64_t right = std::min<int64_t>(binom_sat(cfree - 1 + r, cfree - 1), l - 1);
-      const int64_t m = b - right;
+      const int64_t m = a + revolve_split(b - a, cfree + 1);
       const int64_t slot_m = n_snap - cfree;
       if (hlb_status st = restore(slot_a)) return st;
       if (hlb_status st = advance(m - a, c->adj_slots[slot_m])) return st;  // m - a >= 1
@@ -1488,6 +1528,12 @@ struct Revolve {
 };
 
 }  // namespace
+
+extern "C" hlb_status hlb_revolve_forward_steps(int64_t n, int32_t n_snap, int64_t *steps) {
+  if (n < 1 || n_snap < 1 || n_snap > 4096 || !steps) return fail(HLB_EINVAL, "need n >= 1, 1 <= n_snap <= 4096, steps");
+  *steps = revolve_forward_steps(0, n, n_snap - 1);
+  return HLB_OK;
+}
 
 extern "C" hlb_status hlb_adjoint_run(hlb_ctx *c, int64_t n, int64_t obj_t0, int64_t obj_t1, int32_t n_snap,
                                       double *J, double *dJ_dA, double *dJ_dphi, int64_t *forward_steps) {

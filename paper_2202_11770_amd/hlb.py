@@ -114,6 +114,7 @@ _SIGS = {
     "hlb_step_edge": [_P],
     "hlb_step_mid": [_P],
     "hlb_adjoint_run": [_P, _i64, _i64, _i64, _i32, _P, _P, _P, ctypes.POINTER(_i64)],
+    "hlb_revolve_forward_steps": [_i64, _i32, ctypes.POINTER(_i64)],
     "hlb_last_error": [],
 }
 EXPORTED = tuple(_SIGS)
@@ -406,6 +407,13 @@ def hlb_set_objective(ctx, kind: int, weights=None):
     per-iolet weights [n_iolets]."""
     w, wp = (None, None) if weights is None else _host(weights, np.float64)
     _check(load().hlb_set_objective(ctx, int(kind), wp), "hlb_set_objective")
+
+
+def hlb_revolve_forward_steps(n: int, n_snap: int) -> int:
+    """Forward steps hlb_adjoint_run takes for n steps with n_snap snapshots."""
+    v = ctypes.c_int64()
+    _check(load().hlb_revolve_forward_steps(int(n), int(n_snap), ctypes.byref(v)), "hlb_revolve_forward_steps")
+    return int(v.value)
 
 
 def hlb_adjoint_run(ctx, n: int, obj_t0: int, obj_t1: int, n_snap: int, want_dA=True, want_dphi=True):

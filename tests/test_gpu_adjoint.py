@@ -111,9 +111,10 @@ def test_checkpoint_count_does_not_change_result():
     sim = _gpu_sim(g, tau, tables, phi)
     ref = hlb.hlb_adjoint_run(sim.ctx, nsteps, w0, w1, nsteps + 1)
     assert ref[3] == nsteps - 1  # enough slots: one forward sweep
-    for ns in (1, 2, 7):
+    for ns in (1, 2, 3, 7):
         out = hlb.hlb_adjoint_run(sim.ctx, nsteps, w0, w1, ns)
         say(f"n_snap {ns}: forward steps {out[3]}")
+        assert out[3] == hlb.hlb_revolve_forward_steps(nsteps, ns)  # the optimal count
         assert abs(out[0] - ref[0]) <= 1e-14 * abs(ref[0])
         assert rel(out[1], ref[1]) <= 1e-13 and rel(out[2], ref[2]) <= 1e-13
     # the state is left where it was, so a plain step still matches
