@@ -84,6 +84,19 @@ __device__ inline void link_masks(const GatherArgs &a, int64_t p, uint32_t &wall
 // state g lives only until its moments are known.  mu is read once and nu
 // written once per step, both far beyond the caches: non-temporal (measured
 // 12% off the reverse step with the same in k_adj_stream).
+//
+// Without porosity the porosity derivative's collision part is taken here
+// too: a wall link j gathers h_j = w_j rho0 - g_j's complement directly
+// (g_j = s_{t-1}(p, opp(j))), so with h_j = w_j rho0 - g_j and
+// nu_j = (1 - omega) mu_j + omega (a + b.(c_j - u)),
+//   sum over wall links of nu_j h_j
+//     = (1 - omega) sum mu_j h_j + omega (a H + b.(Hc - u H)),
+//   H = sum h_j,  Hc = sum h_j c_j,
+// and mu is loaded with the gather so that sum mu_j h_j is formed before g
+// is dropped.  This spares k_adj_boundary the scattered loads of nu and
+// s_{t-1} at every wall site; it then adds only the objective's part.  With
+// porosity the gathered value is not s_{t-1} itself, and k_adj_boundary
+// keeps the whole term.
 template <bool POROUS>
 __global__ __launch_bounds__(kBlock) void k_adj_collide(AdjArgs A) {
   const GatherArgs &a = A.a;
@@ -91,21 +104,44 @@ __global__ __launch_bounds__(kBlock) void k_adj_collide(AdjArgs A) {
   if (p >= a.np || A.order[p] < 0) return;
   const int32_t p32 = (int32_t)p;
   double rho, ux, uy, uz;
+  double m[Q];
+  double hm = 0.0, h0 = 0.0, hx = 0.0, hy = 0.0, hz = 0.0;
+  uint32_t wall = 0;
+  if constexpr (!POROUS) {
+    uint32_t iol;
+    link_masks(a, p, wall, iol);
+  }
   {
     double g[Q];
     if (p < a.io_begin)
       gather<false, POROUS, false>(A.S, p, p / kBlock, a, g);
     else
       gather<true, POROUS, false>(A.S, p, 0, a, g);
+    if constexpr (!POROUS) {
+#pragma unroll
+      for (int i = 0; i < Q; ++i) m[i] = __builtin_nontemporal_load(&A.mu[pidx(p32, i)]);
+    }
     double dr, jx, jy, jz;
     moments<false>(g, 0.0, dr, rho, jx, jy, jz);
     ux = jx / rho;
     uy = jy / rho;
     uz = jz / rho;
-  }
-  double m[Q];
+    if constexpr (!POROUS) {
 #pragma unroll
-  for (int i = 0; i < Q; ++i) m[i] = __builtin_nontemporal_load(&A.mu[pidx(p32, i)]);
+      for (int j = 1; j < Q; ++j) {
+        const double h = ((wall >> (j - 1)) & 1u) ? wgt<double>(j) * a.rho0 - g[j] : 0.0;
+        hm += m[j] * h;
+        h0 += h;
+        hx += h * cx(j);
+        hy += h * cy(j);
+        hz += h * cz(j);
+      }
+    }
+  }
+  if constexpr (POROUS) {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) m[i] = __builtin_nontemporal_load(&A.mu[pidx(p32, i)]);
+  }
   double ea, ebx, eby, ebz;
   eq_transpose(m, rho, ux, uy, uz, ea, ebx, eby, ebz);
 #pragma unroll
@@ -113,6 +149,11 @@ __global__ __launch_bounds__(kBlock) void k_adj_collide(AdjArgs A) {
     __builtin_nontemporal_store(
         (1.0 - A.omega) * m[j] + A.omega * (ea + ebx * (cx(j) - ux) + eby * (cy(j) - uy) + ebz * (cz(j) - uz)),
         &A.nu[pidx(p32, j)]);
+  if constexpr (!POROUS) {
+    if (wall)
+      A.dphi[p] += (1.0 - A.omega) * hm +
+                   A.omega * (ea * h0 + ebx * (hx - ux * h0) + eby * (hy - uy * h0) + ebz * (hz - uz * h0));
+  }
 }
 
 // The rest of nu_t and the parameter derivatives of the update t-1 -> t, at
@@ -203,6 +244,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) 
 #pragma unroll
       for (int i = 0; i < Q; ++i) m[i] = ((need >> i) & 1u) ? A.nu[pidx(p32, i)] : 0.0;
     }
+    // porosity derivative at the current porosity (also where none is set):
+    // the whole term with porosity, else only the objective's part (the
+    // collision's part is added by k_adj_collide)
+    double dphi = 0.0;
     if (w > 0.0) {
       // dWSS/d(g - f^eq)_i = fac (c_i.n)(e.c_i), e = s/|s|; then through f^eq(g)
       double wd[Q];
@@ -212,12 +257,18 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) 
       double wa, wbx, wby, wbz;
       eq_transpose(wd, rho, ux, uy, uz, wa, wbx, wby, wbz);
 #pragma unroll
-      for (int j = 0; j < Q; ++j) m[j] += wd[j] - (wa + wbx * (cx(j) - ux) + wby * (cy(j) - uy) + wbz * (cz(j) - uz));
+      for (int j = 0; j < Q; ++j) {
+        const double inc = wd[j] - (wa + wbx * (cx(j) - ux) + wby * (cy(j) - uy) + wbz * (cz(j) - uz));
+        m[j] += inc;
+        if (!POROUS && j > 0 && (wall & (1u << (j - 1))))
+          dphi += inc * (wgt<double>(j) * a.rho0 - A.S[pidx(p32, opp(j))]);
+      }
     }
-    double dphi = 0.0;  // at the current porosity (also where none is set)
+    if constexpr (POROUS) {
 #pragma unroll
-    for (int i = 1; i < Q; ++i)
-      if (wall & (1u << (i - 1))) dphi += m[i] * (wgt<double>(i) * a.rho0 - A.S[pidx(p32, opp(i))]);
+      for (int i = 1; i < Q; ++i)
+        if (wall & (1u << (i - 1))) dphi += m[i] * (wgt<double>(i) * a.rho0 - A.S[pidx(p32, opp(i))]);
+    }
     if (iol) {
       const bool flux = A.objective == HLB_OBJ_IOLET_FLUX && A.in_window;
       double ox, oy, oz;  // velocity at t-1 (pressure rule)
@@ -254,7 +305,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) 
       }
       if (flux) jsum = q;
     }
-    A.dphi[p] += dphi;
+    if (dphi != 0.0) A.dphi[p] += dphi;
     if (w > 0.0) {
 #pragma unroll
       for (int i = 0; i < Q; ++i) A.nu[pidx(p32, i)] = m[i];
@@ -385,14 +436,19 @@ hipError_t launch_adjoint_step(const LaunchCfg &cfg, const Layout &L, const DevP
   A.objective = b.objective;
   A.w = b.w;
   const unsigned grid = blocks_of(L.np);
-  const unsigned grid_b = blocks_of(std::max<int64_t>(b.n_blist, 1));
   if (cfg.porous) {
     k_adj_collide<true><<<grid, kBlock, 0, s>>>(A);
-    if (b.n_blist > 0) k_adj_boundary<true><<<grid_b, kBlock, 0, s>>>(A, b.blist, b.n_blist);
+    if (b.n_blist > 0)
+      k_adj_boundary<true><<<blocks_of(b.n_blist), kBlock, 0, s>>>(A, b.blist, b.n_blist);
     k_adj_stream<true><<<grid, kBlock, 0, s>>>(A);
   } else {
     k_adj_collide<false><<<grid, kBlock, 0, s>>>(A);
-    if (b.n_blist > 0) k_adj_boundary<false><<<grid_b, kBlock, 0, s>>>(A, b.blist, b.n_blist);
+    // without porosity and outside the WSS objective's window only the
+    // sites with iolet links (the list's tail) have terms left
+    const bool walls_too = b.objective == HLB_OBJ_WSS && in_window;
+    const int32_t *list = walls_too ? b.blist : b.blist + b.n_blist_wall;
+    const int64_t n_list = walls_too ? b.n_blist : b.n_blist - b.n_blist_wall;
+    if (n_list > 0) k_adj_boundary<false><<<blocks_of(n_list), kBlock, 0, s>>>(A, list, n_list);
     k_adj_stream<false><<<grid, kBlock, 0, s>>>(A);
   }
   return hipGetLastError();

@@ -137,6 +137,7 @@ struct AdjBuffers {
   double *dphi = nullptr;     // [np] porosity derivative per position
   int32_t *blist = nullptr;   // positions of the sites with wall or iolet links, ascending
   int64_t n_blist = 0;
+  int64_t n_blist_wall = 0;   // leading entries below the iolet groups (wall links only)
   int32_t objective = HLB_OBJ_WSS;
   double *w = nullptr;        // [n_iolets] iolet-flux weights (device)
 };

@@ -709,6 +709,8 @@ static hlb_status create_impl(int64_t n, const int32_t *coords, const uint8_t *t
     if ((st = dev_alloc(c, &p, blist.size() * sizeof(int32_t)))) return bail(st);
     c->adj.blist = static_cast<int32_t *>(p);
     c->adj.n_blist = (int64_t)blist.size();
+    c->adj.n_blist_wall =
+        (int64_t)(std::lower_bound(blist.begin(), blist.end(), (int32_t)L.io_begin) - blist.begin());
     if ((st = cp(c->adj.blist, blist.data(), blist.size() * sizeof(int32_t)))) return bail(st);
   }
   if (!corr.empty() && (st = cp(c->d.corr, corr.data(), corr.size() * sizeof(double)))) return bail(st);

@@ -52,7 +52,8 @@ def _small_case(nsteps=60, seed=4):
 
 def _gpu_sim(g, tau, tables, phi):
     sim = hlb.Simulation.create(g, tau, tables=tables, adjoint=True)
-    hlb.hlb_set_porosity(sim.ctx, phi)
+    if phi is not None:
+        hlb.hlb_set_porosity(sim.ctx, phi)
     return sim
 
 
@@ -88,9 +89,16 @@ class GpuObjective:
         return float(acc.item())
 
 
-def test_adjoint_matches_oracle_small():
+@pytest.mark.parametrize("porous", [True, False], ids=["porous", "no_porosity"])
+def test_adjoint_matches_oracle_small(porous):
+    """Without a porosity field the porosity derivative (at zero porosity)
+    takes another kernel path: the collision part in k_adj_collide, the
+    objective's part in k_adj_boundary."""
     nsteps, w0, w1, tau = 60, 30, 60, 0.8
     g, tables, phi, ws = _small_case(nsteps)
+    if not porous:
+        phi = None
+    say(f"case: small tortuous {g.n} sites, porous {porous}")
     P = oracle.Problem(g, tau, tables=tables, phi=phi)
     Jr, dAr, dphir = P.adjoint(P.init(), 0, nsteps, w0, w1)
     sim = _gpu_sim(g, tau, tables, phi)

@@ -44,15 +44,19 @@ def _small_case(nsteps=60, seed=4):
     return g, tables, phi, ws
 
 
-def test_flux_adjoint_matches_oracle_small():
+@pytest.mark.parametrize("porous", [True, False], ids=["porous", "no_porosity"])
+def test_flux_adjoint_matches_oracle_small(porous):
     nsteps, w0, w1, tau = 60, 30, 60, 0.8
     g, tables, phi, ws = _small_case(nsteps)
+    if not porous:
+        phi = None
     w = np.array([1.0 if io.kind == G.PRESSURE else 0.5 for io in g.iolets])
-    say(f"case: small tortuous {g.n} sites, {nsteps} steps, window ({w0},{w1}], weights {w}")
+    say(f"case: small tortuous {g.n} sites, {nsteps} steps, window ({w0},{w1}], weights {w}, porous {porous}")
     P = oracle.Problem(g, tau, tables=tables, phi=phi)
     Jr, dTr, dphir = P.adjoint(P.init(), 0, nsteps, w0, w1, weights=w)
     sim = hlb.Simulation.create(g, tau, tables=tables, adjoint=True)
-    hlb.hlb_set_porosity(sim.ctx, phi)
+    if porous:
+        hlb.hlb_set_porosity(sim.ctx, phi)
     hlb.hlb_set_objective(sim.ctx, hlb.HLB_OBJ_IOLET_FLUX, w)
     J, dT, dphi, fw = hlb.hlb_adjoint_run(sim.ctx, nsteps, w0, w1, 4)
     say(f"flux adjoint: J {J:.9e} vs {Jr:.9e}; table rows rel {rel(dT, dTr):.2e}; dphi rel {rel(dphi, dphir):.2e}")
