@@ -67,7 +67,8 @@ struct Layout {
 
 struct DevPtrs {
   void *f[2] = {nullptr, nullptr};  // population buffers, [np/kPopTile][19][kPopTile] of the storage type
-  int32_t *seg_off = nullptr;       // [nseg][kSegRow] bulk+wall source offsets per segment
+  int32_t *seg_off = nullptr;       // [nseg + 1][kSegRow] bulk+wall source offsets per segment
+                                    // (the last row is padding, read by scalar row loads)
   int32_t *seg_base = nullptr;      // [ceil(n0 / kSegBlock)] first segment of each block
   uint8_t *seg_delta = nullptr;     // [n0] segment of each position minus its block's first
   int32_t *nbr_io = nullptr;        // iolet groups' pull table [18][nio]: source position of

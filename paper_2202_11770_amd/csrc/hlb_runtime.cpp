@@ -587,7 +587,9 @@ static hlb_status create_impl(int64_t n, const int32_t *coords, const uint8_t *t
     segid[p] = (int32_t)(nseg - 1);
   }
   L.nseg = nseg;
-  std::vector<int32_t> seg_off((size_t)kSegRow * std::max<int64_t>(nseg, 1), 0);
+  // one padding row after the last segment (read by a wavefront's scalar
+  // row loads, never used)
+  std::vector<int32_t> seg_off((size_t)kSegRow * (nseg + 1), 0);
   std::vector<int32_t> seg_base(std::max<int64_t>(nb0, 1), 0);
   std::vector<uint8_t> seg_delta((size_t)std::max<int64_t>(nb0 * kSegBlock, 1), 0);
 #pragma omp parallel for schedule(static)
