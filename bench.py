@@ -1,22 +1,32 @@
 """Throughput of the sparse D3Q19 LBGK update on one MI355X.
 
-Workload (default): the seeded bifurcating tree of ~2.0e7 fluid sites (seed
+Workload (default): the seeded bifurcating tree of ~2.0e8 fluid sites (seed
 2, 8 branching generations, Murray radii, 30-60 deg branch angles, lengths of
 6-10 radii), tau = 0.6, one Ladd velocity inlet with
 A(s) = 0.02 * (1 - cos(2 pi s / 2000)) / 2 and 256 pressure outlets at
-rho = 1, FP64 storage.  A step is one full LB update of every site (all
-groups), i.e. one pass of the hot path.  The same geometry is also run with
-the shifted FP32 and FP16 storages.
+rho = 1, FP64 storage; the same geometry is also run with the shifted FP32
+and FP16 storages.  A step is one full LB update of every site (all groups),
+i.e. one pass of the hot path.
+
+Error of each storage, stated beside its throughput:
+  - against the FP64 oracle on the error subtree of the same tree (the
+    first-child branch of the generation whose subtree has about 2e6 sites,
+    at the same lattice spacing, with its own Ladd inlet and rho = 1
+    leaves), every site after 1000 steps from rest;
+  - FP32 and FP16 against the FP64 GPU run on the full tree, every site
+    after the same number of steps (compared on the device).
 
 Prints ONE JSON line:
   value       MLUPS of the FP64 run (eq. (9): sites x steps / (s x 1e6))
   roofline    the step kernel (the only kernel of a step) against 8 TB/s:
               algorithmic bytes per launch (38 population loads/stores +
-              18 int32 pull entries per site, times all sites) over its
-              mean launch duration from HIP events on its stream
-  cpu_baseline  the FP64 oracle on the host cores, on a bounded sample of
-              the same workload (a few steps of the full geometry)
+              the pull-table bytes per site, times all sites) over its mean
+              launch duration from HIP events on its stream
+  cpu_baseline  the FP64 oracle on the host cores, timed on its error
+              reference run over the subtree (a bounded sample of the
+              workload)
   storages    MLUPS, step-kernel GB/s and fraction of peak for f64/f32/f16
+  errors_vs_oracle, errors_vs_f64_gpu   the errors above
 """
 from __future__ import annotations
 
@@ -109,12 +119,16 @@ def stored_traffic(storage, n_sites):
     return None
 
 
+ORDER = (None, 0)  # site order of the timed runs and its block width (None, 0: the library's defaults)
+
+
 def run_storage(g, tables, tau, storage, steps, warmup, scheme="pull", windkessel=None, sites_per_thread=0):
     import torch
     from paper_2202_11770_amd import hlb
     t0 = time.time()
     sim = hlb.Simulation.create(g, tau, storage=storage, tables=tables, scheme=scheme,
-                                sites_per_thread=sites_per_thread)
+                                sites_per_thread=sites_per_thread, order_block=ORDER[1],
+                                **({"order": ORDER[0]} if ORDER[0] else {}))
     for k, m in (windkessel or {}).items():
         hlb.hlb_set_windkessel(sim.ctx, k, m)
     info = sim.info()
@@ -139,7 +153,8 @@ def run_storage(g, tables, tau, storage, steps, warmup, scheme="pull", windkesse
     mlups = n * steps / dt / 1e6
     # one step kernel updates every site of every group
     achieved = bpl * n / (st["kernel_ms"] * 1e-3) / 1e9
-    return dict(storage=storage, n_sites=n, bytes_per_lup=bpl, ms_per_step=dt / steps * 1e3,
+    order = {v: k for k, v in hlb.ORDER.items()}[info["order"]]
+    return dict(storage=storage, n_sites=n, bytes_per_lup=bpl, ms_per_step=dt / steps * 1e3, order=order,
                 mlups=mlups, alg_gbs=bpl * n * steps / dt / 1e9, kernel_ms=st["kernel_ms"],
                 event_step_ms=st["step_ms"], kernel_gbs=achieved,
                 frac=achieved / PEAK_GBS, mass=m, mass_residual_rel=r / m)
@@ -319,6 +334,58 @@ def copy_ceiling(nbytes=4 << 30, reps=20):
     return hlb.hlb_copy_bandwidth(nbytes, reps)
 
 
+def error_subtree(target=2_000_000):
+    """The error subtree of the 2e8-site tree: cut from the segment list at
+    the 2e8 tree's lattice spacing, so the full tree is never voxelised for
+    it.  Its Ladd inlet takes the benchmark's A(s), its leaves rho = 1."""
+    import numpy as np
+    from paper_2202_11770_amd import geometry as G
+    seg = G.tree_segments(2, 8, scale=TREE_SCALE_200M, origin=(0.5, 0.5, -0.5))
+    sub = G.subtree(segments=seg, scale=TREE_SCALE_200M, target_sites=target)
+    tabs = [inlet_table() if io.kind == G.VELOCITY else np.array([1.0]) for io in sub.iolets]
+    return sub, tabs
+
+
+def errors_vs_oracle(storages, tau, steps=1000):
+    """Every storage against the FP64 oracle on the error subtree, every site
+    after `steps` steps from rest.  The oracle run is timed: it is the CPU
+    baseline (a bounded sample of the workload's own geometry)."""
+    import numpy as np
+    import oracle
+    from paper_2202_11770_amd import hlb
+    sub, tabs = error_subtree()
+    log(f"error subtree: {sub.n} sites, {len(sub.iolets)} iolets; oracle {steps} steps")
+    P = oracle.Problem(sub, tau, tables=tabs)
+    f = P.init()
+    t0 = time.perf_counter()
+    P.run(f, 0, steps)
+    dt = time.perf_counter() - t0
+    rr, ur, wr = P.macros(f)
+    cores = oracle.threads()
+    cpu = {"value": round(sub.n * steps / dt / 1e6, 3), "unit": "MLUPS", "cores": cores, "kind": "oracle",
+           "sample": f"{steps} steps from rest of the {sub.n}-site error subtree of the 2e8-site tree (same "
+                     f"lattice spacing and physics), FP64 AoS push oracle, OpenMP over {cores} threads; "
+                     f"the run that the storages' errors are measured against"}
+    log(f"oracle: {cpu['value']} MLUPS over {dt:.1f}s")
+    un = np.linalg.norm(ur, axis=1).max()
+    out = {"case": f"error subtree of the 2e8-site tree, {sub.n} sites, {steps} steps from rest",
+           "n_sites": int(sub.n), "steps": steps,
+           "metrics": "e_rho = max|rho - rho_ref| / rho0; e_u = max|u - u_ref| / max|u_ref|; "
+                      "e_wss = max|wss - wss_ref| / max wss_ref; rms_u the RMS of |u - u_ref| / max|u_ref|"}
+    for st in storages:
+        sim = hlb.Simulation.create(sub, tau, storage=st, tables=tabs)
+        sim.step(steps)
+        rho, u, wss = sim.macros()
+        sim.close()
+        du = np.linalg.norm(u - ur, axis=1)
+        e = {"e_rho": float(np.abs(rho - rr).max()), "e_u": float(du.max() / un),
+             "e_wss": float(np.abs(wss - wr).max() / wr.max()),
+             "rms_u": float(np.sqrt(np.mean(du ** 2)) / un)}
+        out[st] = {k: float(f"{v:.3g}") for k, v in e.items()}
+        log(f"{st} vs oracle on the subtree: {out[st]}")
+    return out, cpu
+
+
 def cpu_baseline(g, tables, tau, budget_s=15.0):
     import oracle
     P = oracle.Problem(g, tau, tables=tables)
@@ -339,10 +406,12 @@ def cpu_baseline(g, tables, tau, budget_s=15.0):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", default="tree20m", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="tree200m", choices=sorted(WORKLOADS))
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--storages", default=None)
+    ap.add_argument("--order", default=None, help="site order of the timed runs (default: the library's)")
+    ap.add_argument("--order-block", type=int, default=0, help="log2 band/column width of the bands/columns orders")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-copy", action="store_true")
     ap.add_argument("--schemes", default="pull",
@@ -358,9 +427,12 @@ def main():
                     help="also time the workload with every pressure outlet a three-element Windkessel")
     ap.add_argument("--split", type=int, default=0,
                     help="also time the workload as this many partitions with the halo exchange (one GPU)")
-    ap.add_argument("--compare-steps", type=int, default=0,
-                    help="also run every storage for this many steps from rest and report the "
-                         "FP32/FP16 errors against the FP64 GPU run")
+    ap.add_argument("--compare-steps", type=int, default=None,
+                    help="run every storage for this many steps from rest and report the FP32/FP16 errors "
+                         "against the FP64 GPU run (default: 1000 on tree200m, else 0)")
+    ap.add_argument("--error-steps", type=int, default=None,
+                    help="steps of the per-storage comparison with the oracle on the error subtree "
+                         "(default: 1000 on tree200m, else 0)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); the multi-GPU "
@@ -371,6 +443,14 @@ def main():
     tau, def_steps, def_storages, desc = WORKLOADS[args.workload]
     args.steps = args.steps or def_steps
     args.storages = args.storages or def_storages
+    global ORDER
+    if args.order:
+        ORDER = (args.order, args.order_block)
+    big = args.workload == "tree200m"
+    if args.compare_steps is None:
+        args.compare_steps = 1000 if big else 0
+    if args.error_steps is None:
+        args.error_steps = 1000 if big else 0
     t0 = time.time()
     g, tables = workload(args.workload)
     log(f"workload: {args.workload}: {g.n} sites, {len(g.iolets)} iolets, fill {g.meta['fill']:.4f}, "
@@ -411,8 +491,14 @@ def main():
     if copy_gbs:
         log(f"plain copy: {copy_gbs:.0f} GB/s")
     cpu = None
-    if not args.no_cpu_baseline and args.workload == "tree20m":
+    err_or = None
+    if args.error_steps > 0:
+        err_or, cpu_sub = errors_vs_oracle(args.storages.split(","), tau, args.error_steps)
+        if not args.no_cpu_baseline:
+            cpu = cpu_sub
+    if cpu is None and not args.no_cpu_baseline and args.workload == "tree20m":
         cpu = cpu_baseline(g, tables, tau)
+    if cpu is not None:
         log(f"cpu baseline: {cpu}")
     adj = None
     if args.adjoint:
@@ -454,7 +540,7 @@ def main():
         "dtype": {"f64": "f64", "f32": "f32-storage", "f16": "f16-storage"}[main_st],
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {desc}; {g.n} fluid sites, tau {tau}, storage {main_st}",
-                   "n_sites": g.n, "storage": main_st, "order": "lex", "parallelism": "single GPU"},
+                   "n_sites": g.n, "storage": main_st, "order": R["order"], "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(R["kernel_gbs"], 1), "peak": PEAK_GBS, "unit": "GB/s",
                      "frac": round(R["frac"], 4), "traffic": traffic,
                      "kernel": "k_step (all site groups, one launch per step)",
@@ -469,8 +555,11 @@ def main():
                          "gain_vs_f64": round(v["mlups"] / results[main_st]["mlups"], 3),
                          "mass_residual_rel": v["mass_residual_rel"]} for k, v in results.items()},
     }
+    if err_or is not None:
+        out["errors_vs_oracle"] = err_or
     if compare is not None:
-        out["errors_vs_f64_gpu"] = {"steps": args.compare_steps, **compare}
+        out["errors_vs_f64_gpu"] = {"case": f"the full {g.n}-site workload, every site", "steps": args.compare_steps,
+                                    **compare}
     if ab:
         out["schemes"] = ab
     if spt_ab:

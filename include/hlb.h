@@ -86,7 +86,11 @@ typedef enum {
   HLB_ORDER_INPUT = 0,  /* caller order within each group */
   HLB_ORDER_LEX = 1,    /* lexicographic (z, y, x) (default) */
   HLB_ORDER_MORTON = 2, /* Morton (Z-order) curve */
-  HLB_ORDER_BRICK = 3   /* Morton order of 4x4x4 bricks, lexicographic inside */
+  HLB_ORDER_BRICK = 3,  /* Morton order of 4x4x4 bricks, lexicographic inside */
+  HLB_ORDER_BANDS = 4,  /* bands of 2^order_block consecutive y rows, in y
+                           order; lexicographic (z, y, x) inside a band */
+  HLB_ORDER_COLUMNS = 5 /* columns of 2^order_block x 2^order_block in (x, y),
+                           in (y, x) order; lexicographic (z, y, x) inside */
 } hlb_order;
 
 enum { HLB_IOLET_VELOCITY = 0, HLB_IOLET_PRESSURE = 1 };
@@ -136,6 +140,9 @@ typedef struct {
                           used while timing is on.  Results do not depend on
                           it (bit for bit, except where atomics already make
                           the Windkessel outflow order-dependent). */
+  int32_t order_block; /* log2 of the band / column width of
+                          HLB_ORDER_BANDS and HLB_ORDER_COLUMNS, 1..16
+                          (default 6); ignored by the other orders */
 } hlb_options;
 
 /* Order of the fused update (Sec. 3.2 implements push and names pull as
@@ -186,6 +193,24 @@ hlb_status hlb_set_iolet_table(hlb_ctx *ctx, int32_t k, const double *values, in
  * i.e. a fraction phi leaks to a reservoir at rest density.  NULL removes
  * the porosity (plain bounce-back).  Not a rule of the paper. */
 hlb_status hlb_set_porosity(hlb_ctx *ctx, const double *phi);
+
+/* Device-array forms of the two setters above, for callers whose parameters
+ * live on the GPU (torch tensors):
+ *   hlb_set_iolet_table_device: values is a device array of len doubles.
+ *     The values are checked on the device (finite; > 0 for a pressure
+ *     iolet; HLB_EINVAL otherwise, nothing changed).  If len equals the
+ *     iolet's current table length (and no Windkessel model is on), they are
+ *     copied device to device into the library's table, ordered on the
+ *     context stream before later steps; otherwise the library's table
+ *     layout is rebuilt, which reads the len values back to the host once.
+ *   hlb_set_porosity_device: phi is a device array [n_sites] of doubles in
+ *     caller order (NULL removes the porosity); checked on the device
+ *     (every value in [0,1], HLB_EINVAL otherwise, nothing changed) and
+ *     reordered into the library's positions by a kernel.
+ * Both wait for the check's one-word verdict; the caller's array may be
+ * reused once the call has returned. */
+hlb_status hlb_set_iolet_table_device(hlb_ctx *ctx, int32_t k, const void *values, int64_t len);
+hlb_status hlb_set_porosity_device(hlb_ctx *ctx, const void *phi);
 
 /* Reset the state to f = f^eq(rho(x), u(x)) (Sec. 3.1, step 1) at time t0.
  * rho [n] and u [n][3] are host arrays in caller order, or NULL for rho0 and
@@ -258,6 +283,10 @@ typedef struct {
   double step_ms;    /* mean stream time per step, first to last timed event */
   int64_t adj_steps; /* reverse steps of hlb_adjoint_run timed */
   double adj_ms;     /* mean duration of one reverse step (both adjoint kernels) */
+  double mlups;      /* million lattice-site updates per second over step_ms
+                        (eq. (9): updated sites / step_ms); 0 if none timed */
+  double alg_gbs;    /* algorithmic HBM GB/s of the step kernel: bytes_per_lup
+                        (hlb_info_t) x updated sites / kernel_ms; 0 if none timed */
 } hlb_stats_t;
 hlb_status hlb_stats(hlb_ctx *ctx, hlb_stats_t *stats);
 
@@ -369,6 +398,19 @@ hlb_status hlb_set_objective(hlb_ctx *ctx, int32_t kind, const double *weights);
  * storage (HLB_ESTATE otherwise). */
 hlb_status hlb_adjoint_run(hlb_ctx *ctx, int64_t n, int64_t obj_t0, int64_t obj_t1, int32_t n_snap,
                            double *J, double *dJ_dA, double *dJ_dphi, int64_t *forward_steps);
+
+/* hlb_adjoint_run with device outputs (doubles in GPU memory: J [1],
+ * dJ_dA [n_iolets][n], dJ_dphi [n_sites] in caller order; dJ_dA and dJ_dphi
+ * may be NULL), written asynchronously on the context stream: nothing is
+ * read back to the host and the call does not wait for the sweep.  The
+ * objective's finiteness is not checked (the caller reads J).
+ * *forward_steps (host, may be NULL) is known when the call returns.  The
+ * outputs come from the same kernels as those of hlb_adjoint_run: dJ_dphi
+ * is bit for bit the same; J and dJ_dA, which are summed with atomics
+ * (the iolet terms), can differ in the last bits, as between two runs of
+ * either call. */
+hlb_status hlb_adjoint_run_device(hlb_ctx *ctx, int64_t n, int64_t obj_t0, int64_t obj_t1, int32_t n_snap,
+                                  void *J, void *dJ_dA, void *dJ_dphi, int64_t *forward_steps);
 
 /* Forward steps hlb_adjoint_run takes for n >= 1 steps with n_snap
  * snapshots (1 <= n_snap <= 4096), without running anything: for planning

@@ -13,7 +13,8 @@ come from the GPU adjoint sweep with binomial checkpointing (``n_snap``
 device snapshots).  The adjoint runs in the forward call -- one forward and
 one reverse sweep, however many outputs the graph differentiates -- and
 ``backward`` only scales the stored gradients.  torch is used for the
-tensors; every step of the computation runs in libhlb.so.
+tensors and the stream; every step of the computation runs in libhlb.so, and
+the parameters, the objective and the gradients never leave the GPU.
 
 ``IoletFluxObjective`` does the same for the weighted net outflow through
 the iolets, with gradients also for the per-step ghost densities of the
@@ -43,28 +44,43 @@ def fourier_inlet(theta: torch.Tensor, n: int, period: float, base: float = 0.01
 
 def _adjoint(sim, A, R, phi, n: int, obj_t0: int, obj_t1: int, n_snap: int, kind: int, weights):
     """Set the per-step tables (velocity rows from A, pressure rows from R if
-    given) and the porosity, run hlb_adjoint_run; returns J and the gradients
-    of A, R (or None) and phi as tensors like the inputs."""
+    given) and the porosity from the device tensors, run the adjoint sweep
+    with device outputs; returns J and the gradients of A, R (or None) and
+    phi as device tensors like the inputs, and the forward steps taken.
+
+    The library's work is put on torch's current stream of the current
+    device; the setters read the parameters there (inputs on the host are
+    copied there first) and the outputs are written there; gradients are
+    returned on the inputs' devices, so GPU inputs never leave the GPU.  The
+    simulation keeps the tables and the porosity set here (its state and
+    time are left as they were)."""
     info = hlb.hlb_info(sim.ctx)
     t0 = hlb.hlb_time(sim.ctx)
+    dev = torch.device("cuda", torch.cuda.current_device())  # the library's device
+    hlb.hlb_set_stream(sim.ctx, torch.cuda.current_stream(dev).cuda_stream)
     vel = [k for k in range(info["n_iolets"]) if sim.iolet_kinds[k] == hlb.HLB_IOLET_VELOCITY]
     pres = [k for k in range(info["n_iolets"]) if sim.iolet_kinds[k] == hlb.HLB_IOLET_PRESSURE]
     for rows, T in ((vel, A), (pres, R)):
         if T is None:
             continue
-        T_h = T.detach().to("cpu", torch.float64).numpy().reshape(len(rows), n)
+        Td = T.detach().to(dev, torch.float64).reshape(len(rows), n)
         for r, k in enumerate(rows):
             # the update t0+s -> t0+s+1 reads table[(t0 + s) mod n]
-            hlb.hlb_set_iolet_table(sim.ctx, k, np.roll(T_h[r], t0 % n))
-    hlb.hlb_set_porosity(sim.ctx, phi.detach().to("cpu", torch.float64).numpy())
+            hlb.hlb_set_iolet_table_device(sim.ctx, k, torch.roll(Td[r], t0 % n).contiguous())
+    hlb.hlb_set_porosity_device(sim.ctx, phi.detach().to(dev, torch.float64).contiguous())
     hlb.hlb_set_objective(sim.ctx, kind, weights)
+    nio = info["n_iolets"]
+    J = torch.zeros(1, dtype=torch.float64, device=dev)
+    d_tab = torch.zeros(nio, n, dtype=torch.float64, device=dev)
+    dphi = torch.zeros(info["n_sites"], dtype=torch.float64, device=dev)
     try:
-        J, d_tab, dphi, fw = hlb.hlb_adjoint_run(sim.ctx, n, obj_t0, obj_t1, n_snap)
+        fw = hlb.hlb_adjoint_run_device(sim.ctx, n, obj_t0, obj_t1, n_snap, J, d_tab if nio else None, dphi)
     finally:
         hlb.hlb_set_objective(sim.ctx, hlb.HLB_OBJ_WSS)
-    dA = torch.from_numpy(d_tab[vel]).to(A.device, A.dtype).reshape(A.shape)
-    dR = None if R is None else torch.from_numpy(d_tab[pres]).to(R.device, R.dtype).reshape(R.shape)
-    return J, dA, dR, torch.from_numpy(dphi).to(phi.device, phi.dtype), fw
+    # gradients on the inputs' devices (no copy when they live on the GPU)
+    dA = d_tab[vel].to(A.device, A.dtype).reshape(A.shape)
+    dR = None if R is None else d_tab[pres].to(R.device, R.dtype).reshape(R.shape)
+    return J[0].to(A.device), dA, dR, dphi.to(phi.device, phi.dtype), fw
 
 
 class WssObjective(torch.autograd.Function):
@@ -73,7 +89,7 @@ class WssObjective(torch.autograd.Function):
         J, dA, _, dphi, fw = _adjoint(sim, A, None, phi, n, obj_t0, obj_t1, n_snap, hlb.HLB_OBJ_WSS, None)
         ctx.save_for_backward(dA, dphi)
         ctx.forward_steps = fw
-        return torch.tensor(J, dtype=torch.float64, device=A.device)
+        return J.clone()
 
     @staticmethod
     def backward(ctx, gJ):
@@ -95,9 +111,9 @@ class IoletFluxObjective(torch.autograd.Function):
                                        np.asarray(weights, dtype=np.float64))
         ctx.save_for_backward(dA, dR, dphi)
         ctx.forward_steps = fw
-        return torch.tensor(J, dtype=torch.float64, device=A.device)
+        return J.clone()
 
     @staticmethod
     def backward(ctx, gJ):
         dA, dR, dphi = ctx.saved_tensors
-        return gJ * dA, gJ * dR, gJ * dphi, None, None, None, None, None, None
+        return gJ * dA, (None if dR is None else gJ * dR), gJ * dphi, None, None, None, None, None, None

@@ -43,10 +43,13 @@ def build(verbose: bool = False, extra_hipcc=()) -> str:
     aobj = os.path.join(BUILD, "hlb_adjoint.o")
     _run([os.path.join(ROCM, "bin", "hipcc"), *HIPCC_FLAGS, *extra_hipcc, *inc, "-c",
           os.path.join(CSRC, "hlb_adjoint.hip"), "-o", aobj], verbose)
+    xobj = os.path.join(BUILD, "hlb_aux.o")
+    _run([os.path.join(ROCM, "bin", "hipcc"), *HIPCC_FLAGS, *inc, "-c",
+          os.path.join(CSRC, "hlb_aux.hip"), "-o", xobj], verbose)
     _run(["g++", "-O2", "-std=c++17", "-fPIC", "-fopenmp", "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(ROCM, "include"),
           *inc, "-c", os.path.join(CSRC, "hlb_runtime.cpp"), "-o", robj], verbose)
     tmp = LIB + ".tmp"
-    _run(["g++", "-shared", "-fopenmp", kobj, cobj, aobj, robj, "-o", tmp, "-L", os.path.join(ROCM, "lib"),
+    _run(["g++", "-shared", "-fopenmp", kobj, cobj, aobj, xobj, robj, "-o", tmp, "-L", os.path.join(ROCM, "lib"),
           "-Wl,-rpath," + os.path.join(ROCM, "lib"), "-lamdhip64"], verbose)
     os.replace(tmp, LIB)
     return LIB

@@ -18,6 +18,8 @@
 #include <vector>
 
 #include "hlb.h"
+#include "hlb_adjoint.h"
+#include "hlb_aux.h"
 #include "hlb_internal.h"
 
 using namespace hlb;
@@ -81,12 +83,28 @@ inline uint64_t spread3(uint64_t v) {
 }
 inline uint64_t morton(uint64_t x, uint64_t y, uint64_t z) { return spread3(x) | spread3(y) << 1 | spread3(z) << 2; }
 
-uint64_t sfc_key(int order, int64_t id, const int32_t *c) {
+// Extent of the coordinates (max + 1 per axis) and the block width 2^b of
+// the band and column orders.
+struct KeyGeom {
+  uint64_t nx = 1, ny = 1, nz = 1;
+  int b = 6;
+};
+
+// Sort key of a site.  Every key stays below 2^63 (coordinates < 2^20; the
+// mixed-radix keys below are at most about nx ny nz (1 + 2^-b)^2).
+uint64_t sfc_key(int order, int64_t id, const int32_t *c, const KeyGeom &kg) {
   const uint64_t x = (uint64_t)c[0], y = (uint64_t)c[1], z = (uint64_t)c[2];
+  const uint64_t B = uint64_t(1) << kg.b, m = B - 1;
   switch (order) {
     case HLB_ORDER_LEX: return z << 40 | y << 20 | x;
     case HLB_ORDER_MORTON: return morton(x, y, z);
     case HLB_ORDER_BRICK: return morton(x >> 2, y >> 2, z >> 2) << 6 | (z & 3) << 4 | (y & 3) << 2 | (x & 3);
+    case HLB_ORDER_BANDS:  // bands of B rows in y, (z, y, x) inside
+      return ((y >> kg.b) * kg.nz + z) * (B * kg.nx) + (y & m) * kg.nx + x;
+    case HLB_ORDER_COLUMNS: {  // B x B columns in (x, y), (z, y, x) inside
+      const uint64_t nxb = (kg.nx + m) >> kg.b;
+      return (((y >> kg.b) * nxb + (x >> kg.b)) * kg.nz + z) * (B * B) + (y & m) * B + (x & m);
+    }
     default: return (uint64_t)id;
   }
 }
@@ -166,6 +184,10 @@ struct hlb_ctx {
   std::vector<int32_t> order_host;     // [np] caller id per position
   std::vector<hlb_iolet> iolets;
   std::vector<std::vector<double>> tables;
+  int64_t tables_len = 0;              // doubles in d.tables
+  std::vector<int64_t> tab_off;        // offset of each iolet's table in d.tables
+  std::vector<uint8_t> tab_dev;        // 1: d.tables holds a newer table than `tables` (device setter)
+  int32_t *flag_dev = nullptr;         // [1] result of the checks of caller device arrays
   // timing
   bool timing = false;
   std::vector<TimedStep> pool;
@@ -233,6 +255,8 @@ void free_all(hlb_ctx *c) {
   F(c->d.f[0]); F(c->d.f[1]); F(c->d.nbr_io); F(c->d.seg_off); F(c->d.seg_base); F(c->d.seg_delta); F(c->d.order); F(c->d.corr); F(c->d.io); F(c->d.tables);
   F(c->d.phi); F(c->d.acc); F(c->d.partial); F(c->d.io_scratch);
   F(c->d.wk_rho); F(c->d.io_flux); F(c->d.wk);
+  F(c->flag_dev);
+  c->flag_dev = nullptr;
   for (auto &s : c->snaps) { F(s.f[0]); F(s.f[1]); F(s.acc); }
   c->snaps.clear();
   F(c->adj.mu); F(c->adj.nu); F(c->adj.J); F(c->adj.dA); F(c->adj.dphi); F(c->adj.w); F(c->adj.blist);
@@ -260,12 +284,23 @@ hlb_status upload_tables(hlb_ctx *c) {
   const int K = (int)c->iolets.size();
   if (K == 0) return HLB_OK;
   HIP_TRY(hipStreamSynchronize(c->stream));
+  // tables last set from device memory live only in d.tables: fetch them
+  // before the concatenation is rebuilt
+  for (int k = 0; k < K && k < (int)c->tab_dev.size(); ++k)
+    if (c->tab_dev[k]) {
+      HIP_TRY(hipMemcpy(c->tables[k].data(), c->d.tables + c->tab_off[k], c->tables[k].size() * sizeof(double),
+                        hipMemcpyDeviceToHost));
+      c->tab_dev[k] = 0;
+    }
+  c->tab_off.assign(K, 0);
+  c->tab_dev.assign(K, 0);
   std::vector<IoletDev> io(K);
   std::vector<double> all;
   for (int k = 0; k < K; ++k) {
     io[k].kind = c->iolets[k].kind;
     io[k].tab_len = (int32_t)c->tables[k].size();
     io[k].tab_off = (int64_t)all.size();
+    c->tab_off[k] = io[k].tab_off;
     for (int a = 0; a < 3; ++a) io[k].n[a] = c->iolets[k].normal[a];
     io[k].wk = k < (int)c->wk_on.size() ? c->wk_on[k] : 0;
     io[k].pad = 0;
@@ -274,11 +309,14 @@ hlb_status upload_tables(hlb_ctx *c) {
   if (c->d.tables) {
     (void)hipFree(c->d.tables);
     c->d.tables = nullptr;
+    c->dev_bytes -= c->tables_len * (int64_t)sizeof(double);
+    c->tables_len = 0;
   }
   void *p = nullptr;
   hlb_status st = dev_alloc(c, &p, all.size() * sizeof(double));
   if (st) return st;
   c->d.tables = static_cast<double *>(p);
+  c->tables_len = (int64_t)all.size();
   HIP_TRY(hipMemcpy(c->d.tables, all.data(), all.size() * sizeof(double), hipMemcpyHostToDevice));
   if (!c->d.io) {
     st = dev_alloc(c, &p, K * sizeof(IoletDev));
@@ -340,6 +378,23 @@ hlb_status ensure_staging(hlb_ctx *c, int64_t doubles) {
   return HLB_OK;
 }
 
+// Runs launch_check_values on a caller's device array and waits for the
+// verdict: HLB_OK if every value keeps the rule, HLB_EINVAL (with `what`
+// in the message) if one does not.
+hlb_status check_device_values(hlb_ctx *c, const double *v, int64_t n, int mode, const char *what) {
+  if (!c->flag_dev) {
+    void *p = nullptr;
+    if (hlb_status st = dev_alloc(c, &p, sizeof(int32_t))) return st;
+    c->flag_dev = static_cast<int32_t *>(p);
+  }
+  HIP_TRY(launch_check_values(v, n, mode, c->flag_dev, c->stream));
+  int32_t bad = 0;
+  HIP_TRY(hipMemcpyAsync(&bad, c->flag_dev, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  if (bad) return fail(HLB_EINVAL, "%s", what);
+  return HLB_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -357,6 +412,7 @@ hlb_status hlb_default_options(hlb_options *opt) {
   opt->scheme = HLB_SCHEME_PULL;
   opt->sites_per_thread = 0;
   opt->graph_steps = 0;
+  opt->order_block = 6;
   return HLB_OK;
 }
 
@@ -376,7 +432,9 @@ static hlb_status create_impl(int64_t n, const int32_t *coords, const uint8_t *t
   hlb_default_options(&opt);
   if (opt_in) opt = *opt_in;
   if (opt.storage < HLB_F64 || opt.storage > HLB_F16_SHIFTED) return fail(HLB_EINVAL, "bad storage %d", opt.storage);
-  if (opt.order < HLB_ORDER_INPUT || opt.order > HLB_ORDER_BRICK) return fail(HLB_EINVAL, "bad order %d", opt.order);
+  if (opt.order < HLB_ORDER_INPUT || opt.order > HLB_ORDER_COLUMNS) return fail(HLB_EINVAL, "bad order %d", opt.order);
+  if (opt.order_block < 1 || opt.order_block > 16)
+    return fail(HLB_EINVAL, "order_block must be in 1..16 (got %d)", opt.order_block);
   if (!(opt.rho0 > 0.0) || !std::isfinite(opt.rho0)) return fail(HLB_EINVAL, "rho0 must be finite and > 0");
   if ((opt.adjoint != 0 && opt.adjoint != 1) || opt.max_device_bytes < 0 || opt.xcd_remap < 0 ||
       opt.xcd_remap > (1 << 20))
@@ -498,12 +556,19 @@ static hlb_status create_impl(int64_t n, const int32_t *coords, const uint8_t *t
       const int g = group_of(type[x]);
       grp[g][fill[g]++] = KeyId(0, (int32_t)x);
     }
+    KeyGeom kg;
+    kg.b = opt.order_block;
+    for (int64_t x = 0; x < n; ++x) {
+      kg.nx = std::max<uint64_t>(kg.nx, (uint64_t)coords[3 * x] + 1);
+      kg.ny = std::max<uint64_t>(kg.ny, (uint64_t)coords[3 * x + 1] + 1);
+      kg.nz = std::max<uint64_t>(kg.nz, (uint64_t)coords[3 * x + 2] + 1);
+    }
     for (int g = 0; g < kGroups; ++g) {
       auto &v = grp[g];
 #pragma omp parallel for schedule(static)
       for (int64_t k = 0; k < (int64_t)v.size(); ++k) {
         const int32_t x = v[k].second;
-        uint64_t key = sfc_key(opt.order, x, coords + 3 * (int64_t)x);
+        uint64_t key = sfc_key(opt.order, x, coords + 3 * (int64_t)x, kg);
         // a partition's edge sites lead the bulk+wall group (bit 63 is
         // unused by every order's key)
         if (g == 0 && role && role[x] != HLB_PART_EDGE) key |= uint64_t(1) << 63;
@@ -750,6 +815,7 @@ hlb_status hlb_set_iolet_table(hlb_ctx *c, int32_t k, const double *v, int64_t l
       if (!(v[s] > 0.0)) return fail(HLB_EINVAL, "ghost density must be > 0");
   if (hlb_status st = bind(c)) return st;
   c->tables[k].assign(v, v + len);
+  if (k < (int32_t)c->tab_dev.size()) c->tab_dev[k] = 0;  // the host copy is now the newer one
   if (k < (int32_t)c->wk_on.size() && c->wk_on[k]) {  // a table replaces the Windkessel
     c->wk_on[k] = 0;
     c->n_wk--;
@@ -842,6 +908,59 @@ hlb_status hlb_set_porosity(hlb_ctx *c, const double *phi) {
   HIP_TRY(hipMemcpy(c->d.phi, h.data(), np * sizeof(double), hipMemcpyHostToDevice));
   c->cfg.porous = true;
   return HLB_OK;
+}
+
+hlb_status hlb_set_porosity_device(hlb_ctx *c, const void *phi) {
+  if (hlb_status st = check_ctx(c)) return st;
+  if (hlb_status st = bind(c)) return st;
+  if (!phi) {
+    c->cfg.porous = false;
+    return HLB_OK;
+  }
+  const double *v = static_cast<const double *>(phi);
+  if (hlb_status st = check_device_values(c, v, c->L.n_sites, kCheckUnit, "a porosity value is not in [0,1]"))
+    return st;
+  if (!c->d.phi) {
+    void *p = nullptr;
+    if (hlb_status st = dev_alloc(c, &p, c->L.np * sizeof(double))) return st;
+    c->d.phi = static_cast<double *>(p);
+  }
+  HIP_TRY(launch_from_caller(v, c->d.order, c->L.np, c->d.phi, c->stream));
+  c->cfg.porous = true;
+  return HLB_OK;
+}
+
+hlb_status hlb_set_iolet_table_device(hlb_ctx *c, int32_t k, const void *values, int64_t len) {
+  if (hlb_status st = check_ctx(c)) return st;
+  if (k < 0 || k >= (int32_t)c->iolets.size()) return fail(HLB_EINVAL, "iolet %d out of range", k);
+  if (!values || len < 1 || len > (1ll << 31)) return fail(HLB_EINVAL, "table must have 1..2^31 values");
+  if (hlb_status st = bind(c)) return st;
+  const double *v = static_cast<const double *>(values);
+  const bool pressure = c->iolets[k].kind == HLB_IOLET_PRESSURE;
+  if (hlb_status st = check_device_values(c, v, len, pressure ? kCheckPositive : kCheckFinite,
+                                          pressure ? "a ghost density is not finite and > 0"
+                                                   : "a table value is not finite"))
+    return st;
+  const bool wk = k < (int32_t)c->wk_on.size() && c->wk_on[k];
+  if (!wk && len == (int64_t)c->tables[k].size() && k < (int32_t)c->tab_off.size()) {
+    // same length: overwrite the iolet's run of the concatenated table in place
+    HIP_TRY(hipMemcpyAsync(c->d.tables + c->tab_off[k], v, (size_t)len * sizeof(double), hipMemcpyDeviceToDevice,
+                           c->stream));
+    c->tab_dev[k] = 1;
+    return HLB_OK;
+  }
+  // a new length (or a Windkessel to replace): the concatenation is rebuilt
+  // from the host copies
+  std::vector<double> h((size_t)len);
+  HIP_TRY(hipMemcpyAsync(h.data(), v, (size_t)len * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  c->tables[k] = std::move(h);
+  if (k < (int32_t)c->tab_dev.size()) c->tab_dev[k] = 0;
+  if (wk) {
+    c->wk_on[k] = 0;
+    c->n_wk--;
+  }
+  return upload_tables(c);
 }
 
 hlb_status hlb_create(int64_t n, const int32_t *coords, const uint8_t *type, const int32_t *nbr, double tau,
@@ -1271,6 +1390,12 @@ hlb_status hlb_stats(hlb_ctx *c, hlb_stats_t *s) {
   s->step_ms = c->sum_step / k;
   s->adj_steps = c->adj_steps_timed;
   s->adj_ms = c->adj_steps_timed > 0 ? c->sum_adj / (double)c->adj_steps_timed : 0.0;
+  // eq. (9) over the mean stream time per step; algorithmic bytes of a step
+  // (hlb_info_t.bytes_per_lup per site) over the mean step-kernel duration
+  const double n_upd = (double)(c->L.n_sites - c->L.n_ghost);
+  const double bpl = 38.0 * (double)storage_bytes(c->cfg.storage) + (double)c->table_bytes / (double)c->L.n_sites;
+  s->mlups = s->step_ms > 0.0 ? n_upd / (s->step_ms * 1e-3) / 1e6 : 0.0;
+  s->alg_gbs = s->kernel_ms > 0.0 ? bpl * n_upd / (s->kernel_ms * 1e-3) / 1e9 : 0.0;
   return HLB_OK;
 }
 
@@ -1539,10 +1664,15 @@ extern "C" hlb_status hlb_revolve_forward_steps(int64_t n, int32_t n_snap, int64
   return HLB_OK;
 }
 
-extern "C" hlb_status hlb_adjoint_run(hlb_ctx *c, int64_t n, int64_t obj_t0, int64_t obj_t1, int32_t n_snap,
-                                      double *J, double *dJ_dA, double *dJ_dphi, int64_t *forward_steps) {
-  if (hlb_status st = check_ctx(c)) return st;
-  if (n < 1 || n_snap < 1 || n_snap > 4096 || !J) return fail(HLB_EINVAL, "need n >= 1, 1 <= n_snap <= 4096, J");
+namespace {
+
+// The forward and reverse sweeps of hlb_adjoint_run, asynchronous on the
+// context stream.  The objective, the table-value derivatives and the
+// porosity derivatives (per position) are left in c->adj; the caller's
+// state, time and flux bookkeeping are put back.
+hlb_status adjoint_sweep(hlb_ctx *c, int64_t n, int64_t obj_t0, int64_t obj_t1, int32_t n_snap,
+                         int64_t *forward_steps) {
+  if (n < 1 || n_snap < 1 || n_snap > 4096) return fail(HLB_EINVAL, "need n >= 1, 1 <= n_snap <= 4096");
   if (c->n_wk > 0) return fail(HLB_ESTATE, "the adjoint does not cover Windkessel outlets");
   if (c->cfg.storage != HLB_F64 || !c->adj_on || c->cfg.scheme != HLB_SCHEME_PULL)
     return fail(HLB_ESTATE, "the adjoint needs FP64 storage and opt.adjoint = 1 at creation");
@@ -1556,7 +1686,9 @@ extern "C" hlb_status hlb_adjoint_run(hlb_ctx *c, int64_t n, int64_t obj_t0, int
     c->adj.nu = static_cast<double *>(p);
     if (hlb_status st = dev_alloc(c, &p, (size_t)np * sizeof(double))) return st;
     c->adj.dphi = static_cast<double *>(p);
-    if (hlb_status st = dev_alloc(c, &p, sizeof(double))) return st;
+    // [0] the objective; [1, 5) the caller's flux accumulators while the
+    // sweep runs; from kAdjJPart the collide kernel's per-workgroup sums
+    if (hlb_status st = dev_alloc(c, &p, (size_t)(kAdjJPart + adj_jpart_slots(np)) * sizeof(double))) return st;
     c->adj.J = static_cast<double *>(p);
   }
   if (c->adj_dA_len < std::max<int64_t>(1, nio * n)) {
@@ -1579,12 +1711,12 @@ extern "C" hlb_status hlb_adjoint_run(hlb_ctx *c, int64_t n, int64_t obj_t0, int
   const int cur0 = c->cur;
   const bool direct0 = c->direct;
   const int64_t t_start = c->t;
-  double acc0[4];
-  HIP_TRY(hipMemcpyAsync(acc0, c->d.acc, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipMemcpyAsync(c->adj.J + 1, c->d.acc, 4 * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
   HIP_TRY(hipMemcpyAsync(c->adj_slots[n_snap], c->d.f[1 - cur0], buf_bytes(c), hipMemcpyDeviceToDevice, c->stream));
   HIP_TRY(launch_zero(c->adj.mu, (int64_t)Q * np, c->stream));
   HIP_TRY(launch_zero(c->adj.dphi, np, c->stream));
   HIP_TRY(launch_zero(c->adj.J, 1, c->stream));
+  HIP_TRY(launch_zero(c->adj.J + kAdjJPart, adj_jpart_slots(np), c->stream));
   HIP_TRY(launch_zero(c->adj.dA, std::max<int64_t>(1, nio * n), c->stream));
   Revolve R;
   R.c = c;
@@ -1596,18 +1728,35 @@ extern "C" hlb_status hlb_adjoint_run(hlb_ctx *c, int64_t n, int64_t obj_t0, int
   R.slot_t.assign(n_snap, 0);
   hlb_status st = R.save(0);
   if (!st) st = R.reverse(t_start, t_start + n, 0, n_snap - 1);
+  if (!st) {
+    hipError_t e = launch_adjoint_finish(c->adj, np, c->stream);
+    if (e != hipSuccess) st = fail(HLB_EDEVICE, "adjoint objective sum: %s", hipGetErrorString(e));
+  }
   // put the caller's state back
   if (!st) {
     hipError_t e = hipMemcpyAsync(c->d.f[cur0], c->adj_slots[0], buf_bytes(c), hipMemcpyDeviceToDevice, c->stream);
     if (e == hipSuccess)
       e = hipMemcpyAsync(c->d.f[1 - cur0], c->adj_slots[n_snap], buf_bytes(c), hipMemcpyDeviceToDevice, c->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(c->d.acc, acc0, 4 * sizeof(double), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(c->d.acc, c->adj.J + 1, 4 * sizeof(double), hipMemcpyDeviceToDevice, c->stream);
     if (e != hipSuccess) st = fail(HLB_EDEVICE, "restoring the state: %s", hipGetErrorString(e));
   }
   c->cur = cur0;
   c->direct = direct0;
   c->t = t_start;
-  if (st) return st;
+  if (!st && forward_steps) *forward_steps = R.fwd;
+  return st;
+}
+
+}  // namespace
+
+extern "C" hlb_status hlb_adjoint_run(hlb_ctx *c, int64_t n, int64_t obj_t0, int64_t obj_t1, int32_t n_snap,
+                                      double *J, double *dJ_dA, double *dJ_dphi, int64_t *forward_steps) {
+  if (hlb_status st = check_ctx(c)) return st;
+  if (!J) return fail(HLB_EINVAL, "J is null");
+  int64_t fwd = 0;
+  if (hlb_status st = adjoint_sweep(c, n, obj_t0, obj_t1, n_snap, &fwd)) return st;
+  const int64_t np = c->L.np, nio = (int64_t)c->iolets.size();
   HIP_TRY(hipMemcpyAsync(J, c->adj.J, sizeof(double), hipMemcpyDeviceToHost, c->stream));
   if (dJ_dA && nio > 0)
     HIP_TRY(hipMemcpyAsync(dJ_dA, c->adj.dA, (size_t)nio * n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
@@ -1620,7 +1769,22 @@ extern "C" hlb_status hlb_adjoint_run(hlb_ctx *c, int64_t n, int64_t obj_t0, int
   if (dJ_dphi)
     for (int64_t q = 0; q < np; ++q)
       if (c->order_host[q] >= 0) dJ_dphi[c->order_host[q]] = dphi_pos[q];
-  if (forward_steps) *forward_steps = R.fwd;
+  if (forward_steps) *forward_steps = fwd;
   if (!std::isfinite(*J)) return fail(HLB_ENUMERIC, "objective is not finite");
+  return HLB_OK;
+}
+
+extern "C" hlb_status hlb_adjoint_run_device(hlb_ctx *c, int64_t n, int64_t obj_t0, int64_t obj_t1, int32_t n_snap,
+                                             void *J, void *dJ_dA, void *dJ_dphi, int64_t *forward_steps) {
+  if (hlb_status st = check_ctx(c)) return st;
+  if (!J) return fail(HLB_EINVAL, "J is null");
+  int64_t fwd = 0;
+  if (hlb_status st = adjoint_sweep(c, n, obj_t0, obj_t1, n_snap, &fwd)) return st;
+  const int64_t nio = (int64_t)c->iolets.size();
+  HIP_TRY(hipMemcpyAsync(J, c->adj.J, sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  if (dJ_dA && nio > 0)
+    HIP_TRY(hipMemcpyAsync(dJ_dA, c->adj.dA, (size_t)nio * n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  if (dJ_dphi) HIP_TRY(launch_to_caller(c->adj.dphi, c->d.order, c->L.np, static_cast<double *>(dJ_dphi), c->stream));
+  if (forward_steps) *forward_steps = fwd;
   return HLB_OK;
 }

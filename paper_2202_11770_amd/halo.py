@@ -192,6 +192,16 @@ class SplitSimulation:
             packed.append(e)
         self._unpack(self._transfer(packed))
 
+    def init_equilibrium(self, rho=None, u=None, t0: int = 0):
+        """Every part to f^eq(rho, u) (global [n] and [n][3] host arrays, or
+        None for rest) at time t0, then the ghosts from their owners."""
+        self.synchronize()
+        for P, ctx in zip(self.parts, self.ctx):
+            r = None if rho is None else np.ascontiguousarray(np.asarray(rho, np.float64)[P.glob])
+            v = None if u is None else np.ascontiguousarray(np.asarray(u, np.float64)[P.glob])
+            hlb.hlb_init_equilibrium(ctx, r, v, t0)
+        self.exchange()
+
     def step(self, n: int = 1):
         torch = self.torch
         for _ in range(n):

@@ -25,12 +25,12 @@ STATUS_NAMES = {0: "HLB_OK", -1: "HLB_EINVAL", -2: "HLB_ENOMEM", -3: "HLB_EDEVIC
                 -5: "HLB_ENUMERIC"}
 HLB_F64, HLB_F32_SHIFTED, HLB_F16_SHIFTED = 0, 1, 2
 STORAGE = {"f64": HLB_F64, "f32": HLB_F32_SHIFTED, "f16": HLB_F16_SHIFTED}
-HLB_ORDER_INPUT, HLB_ORDER_LEX, HLB_ORDER_MORTON, HLB_ORDER_BRICK = 0, 1, 2, 3
+HLB_ORDER_INPUT, HLB_ORDER_LEX, HLB_ORDER_MORTON, HLB_ORDER_BRICK, HLB_ORDER_BANDS, HLB_ORDER_COLUMNS = range(6)
 HLB_IOLET_VELOCITY, HLB_IOLET_PRESSURE = 0, 1
 HLB_SCHEME_PULL, HLB_SCHEME_PUSH = 0, 1
 HLB_LINK_WALL = -1
 SCHEME = {"pull": HLB_SCHEME_PULL, "push": HLB_SCHEME_PUSH}
-ORDER = {"input": 0, "lex": 1, "morton": 2, "brick": 3}
+ORDER = {"input": 0, "lex": 1, "morton": 2, "brick": 3, "bands": 4, "columns": 5}
 Q = 19
 
 
@@ -49,7 +49,7 @@ class hlb_options(ctypes.Structure):
     _fields_ = [("storage", ctypes.c_int32), ("order", ctypes.c_int32), ("xcd_remap", ctypes.c_int32),
                 ("adjoint", ctypes.c_int32), ("rho0", ctypes.c_double), ("max_device_bytes", ctypes.c_int64),
                 ("scheme", ctypes.c_int32), ("sites_per_thread", ctypes.c_int32),
-                ("graph_steps", ctypes.c_int32)]
+                ("graph_steps", ctypes.c_int32), ("order_block", ctypes.c_int32)]
 
 
 class hlb_windkessel(ctypes.Structure):
@@ -68,7 +68,8 @@ class hlb_info_t(ctypes.Structure):
 
 class hlb_stats_t(ctypes.Structure):
     _fields_ = [("steps", ctypes.c_int64), ("kernel_ms", ctypes.c_double), ("step_ms", ctypes.c_double),
-                ("adj_steps", ctypes.c_int64), ("adj_ms", ctypes.c_double)]
+                ("adj_steps", ctypes.c_int64), ("adj_ms", ctypes.c_double), ("mlups", ctypes.c_double),
+                ("alg_gbs", ctypes.c_double)]
 
 
 _P = ctypes.c_void_p
@@ -85,6 +86,8 @@ _SIGS = {
     "hlb_set_stream": [_P, _P],
     "hlb_set_iolet_table": [_P, _i32, _P, _i64],
     "hlb_set_porosity": [_P, _P],
+    "hlb_set_iolet_table_device": [_P, _i32, _P, _i64],
+    "hlb_set_porosity_device": [_P, _P],
     "hlb_init_equilibrium": [_P, _P, _P, _i64],
     "hlb_step": [_P, _i64],
     "hlb_macros": [_P, _P, _P, _P],
@@ -114,6 +117,7 @@ _SIGS = {
     "hlb_step_edge": [_P],
     "hlb_step_mid": [_P],
     "hlb_adjoint_run": [_P, _i64, _i64, _i64, _i32, _P, _P, _P, ctypes.POINTER(_i64)],
+    "hlb_adjoint_run_device": [_P, _i64, _i64, _i64, _i32, _P, _P, _P, ctypes.POINTER(_i64)],
     "hlb_revolve_forward_steps": [_i64, _i32, ctypes.POINTER(_i64)],
     "hlb_last_error": [],
 }
@@ -294,6 +298,26 @@ def hlb_set_porosity(ctx, phi):
     _check(load().hlb_set_porosity(ctx, pp), "hlb_set_porosity")
 
 
+def _dev_f64(x, n, what):
+    """A contiguous FP64 CUDA tensor of n elements (checked, not converted)."""
+    if not (x.is_cuda and x.dtype.is_floating_point and x.element_size() == 8 and x.is_contiguous()
+            and x.numel() == n):
+        raise ValueError(f"{what}: need a contiguous float64 CUDA tensor of {n} elements")
+    return _P(int(x.data_ptr()))
+
+
+def hlb_set_iolet_table_device(ctx, k: int, values):
+    """values: contiguous float64 CUDA tensor (the table of iolet k)."""
+    _check(load().hlb_set_iolet_table_device(ctx, int(k), _dev_f64(values, values.numel(), "table"),
+                                             int(values.numel())), "hlb_set_iolet_table_device")
+
+
+def hlb_set_porosity_device(ctx, phi):
+    """phi: contiguous float64 CUDA tensor [n_sites] in caller order, or None."""
+    pp = None if phi is None else _dev_f64(phi, hlb_info(ctx)["n_sites"], "porosity")
+    _check(load().hlb_set_porosity_device(ctx, pp), "hlb_set_porosity_device")
+
+
 def hlb_init_equilibrium(ctx, rho=None, u=None, t0: int = 0):
     r, rp = _host(rho, np.float64)
     v, vp = _host(u, np.float64)
@@ -360,7 +384,8 @@ def hlb_set_timing(ctx, enable: bool):
 def hlb_stats(ctx) -> dict:
     s = hlb_stats_t()
     _check(load().hlb_stats(ctx, ctypes.byref(s)), "hlb_stats")
-    return dict(steps=s.steps, kernel_ms=s.kernel_ms, step_ms=s.step_ms, adj_steps=s.adj_steps, adj_ms=s.adj_ms)
+    return dict(steps=s.steps, kernel_ms=s.kernel_ms, step_ms=s.step_ms, adj_steps=s.adj_steps, adj_ms=s.adj_ms,
+                mlups=s.mlups, alg_gbs=s.alg_gbs)
 
 
 def hlb_snapshot_alloc(ctx, n_slots: int):
@@ -434,6 +459,20 @@ def hlb_adjoint_run(ctx, n: int, obj_t0: int, obj_t1: int, n_snap: int, want_dA=
     return float(J[0]), dA, dphi, fw.value
 
 
+def hlb_adjoint_run_device(ctx, n: int, obj_t0: int, obj_t1: int, n_snap: int, J, dJ_dA=None, dJ_dphi=None) -> int:
+    """Device outputs (contiguous float64 CUDA tensors): J [1], dJ_dA
+    [n_iolets, n] or None, dJ_dphi [n_sites] or None, written asynchronously
+    on the context stream.  Returns the forward steps taken."""
+    info = hlb_info(ctx)
+    fw = ctypes.c_int64()
+    pJ = _dev_f64(J, 1, "J")
+    pA = None if dJ_dA is None or info["n_iolets"] == 0 else _dev_f64(dJ_dA, info["n_iolets"] * int(n), "dJ_dA")
+    pphi = None if dJ_dphi is None else _dev_f64(dJ_dphi, info["n_sites"], "dJ_dphi")
+    _check(load().hlb_adjoint_run_device(ctx, int(n), int(obj_t0), int(obj_t1), int(n_snap), pJ, pA, pphi,
+                                         ctypes.byref(fw)), "hlb_adjoint_run_device")
+    return fw.value
+
+
 def hlb_copy_bandwidth(nbytes: int = 4 << 30, reps: int = 20) -> float:
     g = ctypes.c_double()
     _check(load().hlb_copy_bandwidth(int(nbytes), int(reps), ctypes.byref(g)), "hlb_copy_bandwidth")
@@ -452,15 +491,21 @@ class Simulation:
     iolet_kinds: list = None
 
     @classmethod
-    def create(cls, geom, tau: float, storage: str = "f64", order: str = "lex", xcd_remap: int = 8,
+    def create(cls, geom, tau: float, storage: str = "f64", order: str | None = None, xcd_remap: int = 8,
                rho0: float = 1.0, max_device_bytes: int = 0, tables=None, adjoint: bool = False,
-               scheme: str = "pull", sites_per_thread: int = 0, graph_steps: int = 0):
+               scheme: str = "pull", sites_per_thread: int = 0, graph_steps: int = 0, order_block: int = 0):
+        """order: the site order (None: the library's default); order_block:
+        log2 of the band / column width of the "bands" and "columns" orders
+        (0: the library's default)."""
         opt = hlb_default_options()
+        if order_block:
+            opt.order_block = int(order_block)
         opt.scheme = SCHEME[scheme]
         opt.sites_per_thread = int(sites_per_thread)
         opt.graph_steps = int(graph_steps)
         opt.storage = STORAGE[storage]
-        opt.order = ORDER[order]
+        if order is not None:
+            opt.order = ORDER[order]
         opt.xcd_remap = int(xcd_remap)
         opt.rho0 = float(rho0)
         opt.max_device_bytes = int(max_device_bytes)

@@ -25,3 +25,23 @@ def errors(rho, u, wss, rho_r, u_r, wss_r, rho0=1.0):
 
 def fmt(e):
     return " ".join(f"{k}={v:.3e}" for k, v in e.items() if v is not None)
+
+
+def random_field(n, seed, drho=0.01, umax=0.02):
+    """Seeded non-uniform start: rho = 1 +- drho (uniform) and a velocity of
+    uniformly random direction and magnitude U(0, umax) at every site, so
+    that every site holds distinct populations."""
+    rng = np.random.default_rng(seed)
+    rho = 1.0 + rng.uniform(-drho, drho, n)
+    u = rng.uniform(-1.0, 1.0, (n, 3))
+    u *= (umax * rng.uniform(0.0, 1.0, n) / np.linalg.norm(u, axis=1))[:, None]
+    return rho, u
+
+
+def check_bars(e, bars, label=""):
+    """Assert every metric named in `bars` is within its bar.  The bars of
+    the reduced-precision storages sit about 3x above the errors measured on
+    MI355X (the kernels round deterministically, so a larger error means a
+    changed computation, not noise)."""
+    bad = {k: (e[k], b) for k, b in bars.items() if e.get(k) is None or not e[k] <= b}
+    assert not bad, f"{label}: over the bar (measured, bar): {bad}"

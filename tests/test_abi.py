@@ -36,7 +36,7 @@ def test_exports_every_declared_symbol():
 def test_default_options():
     o = hlb.hlb_default_options()
     assert (o.storage, o.order, o.xcd_remap, o.adjoint, o.rho0, o.max_device_bytes) == (0, 1, 8, 0, 1.0, 0)
-    assert (o.scheme, o.sites_per_thread, o.graph_steps) == (hlb.HLB_SCHEME_PULL, 0, 0)
+    assert (o.scheme, o.sites_per_thread, o.graph_steps, o.order_block) == (hlb.HLB_SCHEME_PULL, 0, 0, 6)
 
 
 @pytest.fixture(scope="module")
@@ -127,6 +127,15 @@ def test_rejects_bad_options(cyl):
         o.sites_per_thread = bad
         _expect(hlb.HLB_EINVAL, hlb.hlb_create, cyl.coords, cyl.types, cyl.nbr, 0.8, cyl.iolets, o,
                 match="sites_per_thread")
+    for bad in (0, 17):
+        o = hlb.hlb_default_options()
+        o.order = hlb.HLB_ORDER_BANDS
+        o.order_block = bad
+        _expect(hlb.HLB_EINVAL, hlb.hlb_create, cyl.coords, cyl.types, cyl.nbr, 0.8, cyl.iolets, o,
+                match="order_block")
+    o = hlb.hlb_default_options()
+    o.order = 6
+    _expect(hlb.HLB_EINVAL, hlb.hlb_create, cyl.coords, cyl.types, cyl.nbr, 0.8, cyl.iolets, o, match="order")
 
 
 def test_null_arguments():
@@ -141,3 +150,6 @@ def test_null_arguments():
     assert lib.hlb_destroy(None) == hlb.HLB_OK
     assert lib.hlb_time(None, None) == hlb.HLB_EINVAL
     assert lib.hlb_set_objective(None, 0, None) == hlb.HLB_EINVAL
+    assert lib.hlb_set_porosity_device(None, None) == hlb.HLB_EINVAL
+    assert lib.hlb_set_iolet_table_device(None, 0, None, 1) == hlb.HLB_EINVAL
+    assert lib.hlb_adjoint_run_device(None, 1, 0, 1, 1, None, None, None, None) == hlb.HLB_EINVAL

@@ -113,6 +113,77 @@ def test_adjoint_matches_oracle_small(porous):
     sim.close()
 
 
+@pytest.mark.parametrize("objective", ["wss", "flux"])
+def test_device_outputs_and_setters_match_host(objective):
+    """hlb_adjoint_run_device (device J, dJ/dA, dJ/dphi, asynchronous) and
+    the device-array setters (table, porosity) give what the host forms
+    give: the porosity gradient bit for bit, J and the table-value rows to
+    the rounding of their atomic sums (whose order varies from run to run);
+    a second call with another table and porosity, set from device arrays
+    of the same length, overwrites the library's tables in place and still
+    matches the host call."""
+    import torch
+    nsteps, w0, w1, tau = 60, 30, 60, 0.8
+    g, tables, phi, ws = _small_case(nsteps)
+    kind = hlb.HLB_OBJ_WSS if objective == "wss" else hlb.HLB_OBJ_IOLET_FLUX
+    weights = None if objective == "wss" else np.linspace(0.5, 1.5, len(g.iolets))
+    say(f"case: device vs host adjoint outputs, small tortuous {g.n} sites, objective {objective}")
+    sim_h = _gpu_sim(g, tau, tables, phi)
+    hlb.hlb_set_objective(sim_h.ctx, kind, weights)
+    sim_d = _gpu_sim(g, tau, [np.ones(1) * (0.01 if io.kind == G.VELOCITY else 1.0) for io in g.iolets], None)
+    hlb.hlb_set_objective(sim_d.ctx, kind, weights)
+    hlb.hlb_set_stream(sim_d.ctx, torch.cuda.current_stream().cuda_stream)
+    rng = np.random.default_rng(9)
+    for trial in range(2):
+        if trial == 1:
+            tables = [t * (1.0 + 1e-3 * rng.uniform(-1, 1, t.size)) for t in tables]
+            phi = phi * rng.uniform(0.5, 1.0, phi.size)
+            for k, t in enumerate(tables):
+                hlb.hlb_set_iolet_table(sim_h.ctx, k, t)
+            hlb.hlb_set_porosity(sim_h.ctx, phi)
+        for k, t in enumerate(tables):
+            hlb.hlb_set_iolet_table_device(sim_d.ctx, k, torch.tensor(t, dtype=torch.float64, device="cuda"))
+        hlb.hlb_set_porosity_device(sim_d.ctx, torch.tensor(phi, dtype=torch.float64, device="cuda"))
+        J, dA, dphi, fw = hlb.hlb_adjoint_run(sim_h.ctx, nsteps, w0, w1, 4)
+        Jd = torch.zeros(1, dtype=torch.float64, device="cuda")
+        dAd = torch.zeros(len(g.iolets), nsteps, dtype=torch.float64, device="cuda")
+        dphid = torch.zeros(g.n, dtype=torch.float64, device="cuda")
+        fwd = hlb.hlb_adjoint_run_device(sim_d.ctx, nsteps, w0, w1, 4, Jd, dAd, dphid)
+        torch.cuda.synchronize()
+        say(f"trial {trial}: J host {J:.15e} device {float(Jd[0]):.15e}; forward steps {fw} / {fwd}")
+        assert fwd == fw
+        assert abs(float(Jd[0]) - J) <= 1e-14 * abs(J)
+        assert np.abs(dAd.cpu().numpy() - dA).max() <= 1e-14 * np.abs(dA).max()
+        assert np.array_equal(dphid.cpu().numpy(), dphi)
+    # the checks reject out-of-range device values and change nothing
+    bad = torch.tensor(phi, dtype=torch.float64, device="cuda")
+    bad[ws[0]] = 1.5
+    with pytest.raises(hlb.HLBError, match="porosity"):
+        hlb.hlb_set_porosity_device(sim_d.ctx, bad)
+    k_p = [k for k, io in enumerate(g.iolets) if io.kind == G.PRESSURE][0]
+    badt = torch.tensor(tables[k_p], dtype=torch.float64, device="cuda")
+    badt[3] = -1.0
+    with pytest.raises(hlb.HLBError, match="ghost density"):
+        hlb.hlb_set_iolet_table_device(sim_d.ctx, k_p, badt)
+    badt[3] = float("nan")
+    with pytest.raises(hlb.HLBError):
+        hlb.hlb_set_iolet_table_device(sim_d.ctx, 0, badt)
+    Jd2 = torch.zeros(1, dtype=torch.float64, device="cuda")
+    hlb.hlb_adjoint_run_device(sim_d.ctx, nsteps, w0, w1, 4, Jd2)
+    torch.cuda.synchronize()
+    assert abs(float(Jd2[0]) - float(Jd[0])) <= 1e-14 * abs(float(Jd[0]))
+    # hlb_stats: eq. (9) rate and algorithmic bandwidth over the timed steps
+    hlb.hlb_set_timing(sim_h.ctx, True)
+    sim_h.step(20)
+    st = hlb.hlb_stats(sim_h.ctx)
+    info = hlb.hlb_info(sim_h.ctx)
+    assert st["steps"] == 20 and st["mlups"] > 0 and st["alg_gbs"] > 0
+    assert abs(st["mlups"] - g.n / (st["step_ms"] * 1e3)) <= 1e-9 * st["mlups"]
+    assert abs(st["alg_gbs"] - info["bytes_per_lup"] * g.n / (st["kernel_ms"] * 1e6)) <= 1e-9 * st["alg_gbs"]
+    sim_h.close()
+    sim_d.close()
+
+
 def test_checkpoint_count_does_not_change_result():
     nsteps, w0, w1, tau = 60, 20, 50, 0.8
     g, tables, phi, ws = _small_case(nsteps)
@@ -191,16 +262,18 @@ def test_c4_full_protocol_autograd_vs_fd():
     kinds = [io.kind for io in g.iolets]
     tables = [np.array([0.0]) if k == G.VELOCITY else np.array([1.0]) for k in kinds]
     sim = hlb.Simulation.create(g, tau, tables=tables, adjoint=True)
-    theta = torch.tensor(theta0, dtype=torch.float64, requires_grad=True)
-    phi = torch.tensor(phi0, dtype=torch.float64, requires_grad=True)
+    # parameters on the GPU: the objective keeps them, J and the gradients there
+    theta = torch.tensor(theta0, dtype=torch.float64, device="cuda", requires_grad=True)
+    phi = torch.tensor(phi0, dtype=torch.float64, device="cuda", requires_grad=True)
     t = time.time()
     A = fourier_inlet(theta, n, period=float(n))[None, :]
     J = WssObjective.apply(A, phi, sim, n, w0, w1, n_snap)
     J.backward()
     t_adj = time.time() - t
     say(f"adjoint: J = {J.item():.8e} in {t_adj:.2f}s")
-    g_theta = theta.grad.numpy().copy()
-    g_phi = phi.grad.numpy().copy()
+    assert J.is_cuda and theta.grad.is_cuda and phi.grad.is_cuda
+    g_theta = theta.grad.cpu().numpy().copy()
+    g_phi = phi.grad.cpu().numpy().copy()
     Jf = GpuObjective(sim)
     vel = kinds.index(G.VELOCITY)
 

@@ -5,6 +5,12 @@ Ladd inlet, 256 pressure outlets), default order and launch, every storage: a
 few steps from the inlet-amplitude peak, every site compared against the
 oracle; and the adjoint in the benchmark's configuration against central
 differences of the GPU objective.
+
+Every forward case starts from the same seeded non-uniform equilibrium on
+both sides (rho = 1 +- 0.01, |u| <= 0.02 at every site), so that every site,
+the far positions of the 64-bit address path included, holds populations
+that no other site holds: a gather from a wrong site, or a wrong direction,
+changes the result wherever it happens.
 """
 import sys
 import time
@@ -14,7 +20,7 @@ import pytest
 
 import oracle
 from paper_2202_11770_amd import hlb
-from _parity import errors, fmt
+from _parity import check_bars, errors, fmt, random_field
 
 pytestmark = pytest.mark.gpu
 
@@ -30,21 +36,23 @@ def tree20m():
 
 
 def test_tree_20m_parity(tree20m):
-    """Every storage against one oracle run; bars as in the smaller cases
-    (FP64 1e-12; FP32 1e-5; FP16 the stated storage bound)."""
+    """Every storage against one oracle run: FP64 to 1e-12; FP32 and FP16
+    to bars about 3x above their measured errors."""
     g, tables = tree20m
     t0, steps, tau = 1000, 6, 0.6  # start at the inlet amplitude's peak
+    rho0, u0 = random_field(g.n, 11)
     P = oracle.Problem(g, tau, tables=tables)
-    f = P.init()
+    f = P.init(rho0, u0)
     t = time.time()
     P.run(f, t0, steps)
     print(f"oracle {steps} steps in {time.time() - t:.1f}s", flush=True)
     ref = P.macros(f)
     m_ref = P.mass(f)
+    del f
     for st in ("f64", "f32", "f16"):
-        print(f"case: tree {g.n} sites, t0 {t0}, {steps} steps, {st}, default launch", flush=True)
+        print(f"case: tree {g.n} sites, random start, t0 {t0}, {steps} steps, {st}, default launch", flush=True)
         sim = hlb.Simulation.create(g, tau, storage=st, tables=tables)
-        hlb.hlb_init_equilibrium(sim.ctx, None, None, t0)
+        hlb.hlb_init_equilibrium(sim.ctx, rho0, u0, t0)
         sim.step(steps)
         rho, u, wss = sim.macros()
         m, r = hlb.hlb_mass_balance(sim.ctx)
@@ -56,9 +64,9 @@ def test_tree_20m_parity(tree20m):
             assert abs(m - m_ref) / m <= 1e-12
             assert abs(r) / m <= steps * 19 * 2.0 ** -53 / tau
         elif st == "f32":
-            assert e["e_rho"] <= 1e-5 and e["e_u"] <= 1e-5 and e["e_wss"] <= 1e-3
+            check_bars(e, dict(e_rho=5e-8, e_u=1e-6, e_wss=2e-6), "tree20m f32")
         else:
-            assert e["e_rho"] <= 1e-2 and e["e_u"] <= 0.2
+            check_bars(e, dict(e_rho=5e-5, e_u=1e-3, e_wss=2e-3), "tree20m f16")
 
 
 def test_tree_20m_adjoint_vs_finite_differences(tree20m):
@@ -111,7 +119,8 @@ def test_tree_30m_fp64_wide_addressing_parity():
     """Above 4 GiB per population buffer the step kernel forms 64-bit
     addresses instead of 32-bit offsets from a scalar base.  A 3.0e7-site
     tree in FP64 (4.6 GB per buffer) takes that path; every site is
-    compared against the oracle after a few steps from the inlet peak."""
+    compared against the oracle after a few steps from the inlet peak, from
+    a random start."""
     sys.path.insert(0, ".")
     import bench
     t = time.time()
@@ -123,12 +132,14 @@ def test_tree_30m_fp64_wide_addressing_parity():
     assert 19 * info["n_padded"] * 8 > 2 ** 32, "the case must exceed 4 GiB per buffer"
     print(f"case: tree {g.n} sites ({19 * info['n_padded'] * 8 / 1e9:.2f} GB per buffer), t0 {t0}, {steps} steps, f64",
           flush=True)
-    hlb.hlb_init_equilibrium(sim.ctx, None, None, t0)
+    rho0, u0 = random_field(g.n, 12)
+    hlb.hlb_init_equilibrium(sim.ctx, rho0, u0, t0)
     sim.step(steps)
     rho, u, wss = sim.macros()
     sim.close()
     P = oracle.Problem(g, tau, tables=tables)
-    f = P.init()
+    f = P.init(rho0, u0)
+    del rho0, u0
     P.run(f, t0, steps)
     e = errors(rho, u, wss, *P.macros(f))
     print("tree30m f64:", fmt(e), flush=True)
@@ -150,18 +161,20 @@ def test_tree_120m_fp16_wide_addressing_parity():
     assert 19 * info["n_padded"] * 2 > 2 ** 32, "the case must exceed 4 GiB per buffer"
     print(f"case: tree {g.n} sites ({19 * info['n_padded'] * 2 / 1e9:.2f} GB per buffer), t0 {t0}, {steps} steps, f16",
           flush=True)
-    hlb.hlb_init_equilibrium(sim.ctx, None, None, t0)
+    rho0, u0 = random_field(g.n, 13)
+    hlb.hlb_init_equilibrium(sim.ctx, rho0, u0, t0)
     sim.step(steps)
     rho, u, wss = sim.macros()
     sim.close()
     P = oracle.Problem(g, tau, tables=tables)
-    f = P.init()
+    f = P.init(rho0, u0)
+    del rho0, u0
     t = time.time()
     P.run(f, t0, steps)
     print(f"oracle {steps} steps in {time.time() - t:.1f}s", flush=True)
     e = errors(rho, u, wss, *P.macros(f))
     print("tree120m f16:", fmt(e), flush=True)
-    assert e["e_rho"] <= 1e-2 and e["e_u"] <= 0.2
+    check_bars(e, dict(e_rho=5e-5, e_u=1e-3, e_wss=2e-3), "tree120m f16")
 
 
 def test_tree_200m_fp64_parity():
@@ -176,12 +189,14 @@ def test_tree_200m_fp64_parity():
     t0, steps, tau = 1000, 3, 0.6
     print(f"case: tree {g.n} sites, t0 {t0}, {steps} steps, f64", flush=True)
     sim = hlb.Simulation.create(g, tau, tables=tables)
-    hlb.hlb_init_equilibrium(sim.ctx, None, None, t0)
+    rho0, u0 = random_field(g.n, 14)
+    hlb.hlb_init_equilibrium(sim.ctx, rho0, u0, t0)
     sim.step(steps)
     rho, u, wss = sim.macros()
     sim.close()
     P = oracle.Problem(g, tau, tables=tables)
-    f = P.init()
+    f = P.init(rho0, u0)
+    del rho0, u0
     t = time.time()
     P.run(f, t0, steps)
     print(f"oracle {steps} steps in {time.time() - t:.1f}s", flush=True)

@@ -3,13 +3,16 @@ hlb_step_edge / hlb_step_mid, paper_2202_11770_amd/halo.py).
 
 Each site's update reads the same values in the same order whether its
 neighbours are owned or ghost copies, so the split run must reproduce the
-single-domain run bit for bit, in every storage.
+single-domain run bit for bit, in every storage; and, independently of the
+single-domain path, it must match the FP64 oracle site by site.
 """
 import numpy as np
 import pytest
 
+import oracle
 from paper_2202_11770_amd import geometry as G
 from paper_2202_11770_amd import halo, hlb
+from _parity import check_bars, errors, fmt, random_field
 
 pytestmark = pytest.mark.gpu
 
@@ -82,3 +85,47 @@ def test_split_porous_and_errors():
         hlb.hlb_halo_set(ctx, mid, np.ones(1, np.int32), sp.send[0], np.zeros(0, np.int32),
                          np.zeros(0, np.int32), sp.recv[0])
     sp.close()
+
+
+SPLIT_BARS = {  # about 3x the errors measured on MI355X
+    "tree2": {"f32": dict(e_rho=2e-7, e_u=1e-5, e_wss=1e-5), "f16": dict(e_rho=3e-5, e_u=2e-3, e_wss=5e-3)},
+    "tree3": {"f32": dict(e_rho=2e-7, e_u=1e-5, e_wss=1e-5), "f16": dict(e_rho=3e-5, e_u=2e-3, e_wss=5e-3)},
+    "box2": {"f32": dict(e_rho=3e-9, e_u=1e-5, e_wss=1e-5), "f16": dict(e_rho=2e-6, e_u=3e-3, e_wss=2e-2)},
+}
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
+@pytest.mark.parametrize("case", ["tree2", "tree3", "box2"])
+def test_split_against_oracle(case, storage):
+    """The split run against the oracle (not against the single-domain GPU
+    run): a 30k-site tree in 2 slabs with time-varying iolets, a 60k-site
+    tree in 3 slabs, and a sealed box in 2 slabs from a random start (every
+    site distinct, so a halo value put in the wrong ghost slot shows)."""
+    init = None
+    if case == "tree2":
+        (g, tables), tau, steps, k = _tree(), 0.6, 300, 2
+    elif case == "tree3":
+        (g, tables), tau, steps, k = _tree(5, 4, 60000), 0.6, 200, 3
+    else:
+        g, tables, tau, steps, k = G.sealed_box(24, 20, 28), None, 0.7, 150, 2
+        init = random_field(g.n, 31)
+    print(f"case: split {case} {g.n} sites, {k} parts, {steps} steps, {storage}, vs oracle", flush=True)
+    P = oracle.Problem(g, tau, tables=tables)
+    f = P.init(*init) if init else P.init()
+    P.run(f, 0, steps)
+    ref = P.macros(f)
+    sp = halo.SplitSimulation(g, tau, storage=storage, tables=tables, nparts=k)
+    if init:
+        sp.init_equilibrium(*init)
+    sp.step(steps)
+    sp.synchronize()
+    got = sp.macros()
+    m = sp.mass()
+    sp.close()
+    e = errors(*got, *ref)
+    print(f"split {case} {storage} vs oracle:", fmt(e), flush=True)
+    if storage == "f64":
+        assert e["e_rho"] <= 1e-12 and e["e_u"] <= 1e-12 and e["e_wss"] <= 1e-10
+        assert abs(m - P.mass(f)) <= 1e-12 * m
+    else:
+        check_bars(e, SPLIT_BARS[case][storage], f"split {case} {storage}")

@@ -34,8 +34,9 @@ def _oracle_run(g, tau, steps, tables=None, phi=None, init=None):
     return P, f
 
 
-def _gpu_run(g, tau, steps, storage="f64", order="lex", xcd=8, tables=None, phi=None, init=None):
-    sim = hlb.Simulation.create(g, tau, storage=storage, order=order, xcd_remap=xcd, tables=tables)
+def _gpu_run(g, tau, steps, storage="f64", order="lex", xcd=8, tables=None, phi=None, init=None, order_block=0):
+    sim = hlb.Simulation.create(g, tau, storage=storage, order=order, xcd_remap=xcd, tables=tables,
+                                order_block=order_block)
     if phi is not None:
         hlb.hlb_set_porosity(sim.ctx, phi)
     if init is not None:
@@ -99,16 +100,17 @@ def test_tree_fp64_time_varying_iolets():
     sim.close()
 
 
-@pytest.mark.parametrize("order,xcd", [("input", 8), ("lex", 0), ("morton", 1 << 20), ("brick", 3)])
-def test_site_order_is_invisible(order, xcd):
+@pytest.mark.parametrize("order,xcd,block", [("input", 8, 0), ("lex", 0, 0), ("morton", 1 << 20, 0), ("brick", 3, 0),
+                                             ("bands", 8, 3), ("bands", 8, 6), ("columns", 8, 4)])
+def test_site_order_is_invisible(order, xcd, block):
     """The update of a site reads the same values whatever the internal
     order, so every order gives bit-identical results."""
     g = _small_tree()
     tabs = _tree_tables(g)
-    say(f"case: order {order} xcd {xcd}")
+    say(f"case: order {order} xcd {xcd} block {block}")
     ref = _gpu_run(g, 0.6, 150, tables=tabs)
     a = ref.macros()
-    sim = _gpu_run(g, 0.6, 150, order=order, xcd=xcd, tables=tabs)
+    sim = _gpu_run(g, 0.6, 150, order=order, xcd=xcd, tables=tabs, order_block=block)
     b = sim.macros()
     for x, y in zip(a, b):
         assert np.array_equal(x, y)

@@ -1,8 +1,9 @@
 """Precision form: populations stored as FP32 / FP16 deviations f - w rho0,
 collided in FP32, against the FP64 oracle.
 
-Targets: FP32 e_rho, e_u <= 1e-5 (relative metrics of tests/_parity.py);
-FP16 errors are stated (printed) and only bounded loosely here.
+Targets: FP32 e_rho, e_u, e_wss <= 1e-5 (relative metrics of
+tests/_parity.py); FP16 errors are stated.  Each case's bars sit about 3x
+above the errors measured on MI355X.
 """
 import numpy as np
 import pytest
@@ -10,7 +11,7 @@ import pytest
 import oracle
 from paper_2202_11770_amd import geometry as G
 from paper_2202_11770_amd import hlb
-from _parity import errors, fmt
+from _parity import check_bars, errors, fmt
 
 pytestmark = pytest.mark.gpu
 
@@ -22,6 +23,12 @@ def _run(g, tau, steps, storage, tables=None):
     m, r = hlb.hlb_mass_balance(sim.ctx)
     sim.close()
     return out, m, r
+
+
+BARS = {
+    "cylinder": {"f32": dict(e_rho=2e-8, e_u=1e-5, e_wss=5e-6), "f16": dict(e_rho=5e-5, e_u=5e-3, e_wss=3e-3)},
+    "tree": {"f32": dict(e_rho=3e-7, e_u=1e-5, e_wss=2e-5), "f16": dict(e_rho=3e-5, e_u=2e-3, e_wss=5e-3)},
+}
 
 
 @pytest.mark.parametrize("case", ["cylinder", "tree"])
@@ -44,6 +51,5 @@ def test_storage_errors(case):
         res[st] = errors(rho, u, wss, *ref)
         print(f"{case} {st}: {fmt(res[st])} mass_residual_rel={r / m:.2e}", flush=True)
     assert res["f64"]["e_rho"] <= 1e-12 and res["f64"]["e_u"] <= 1e-12
-    assert res["f32"]["e_rho"] <= 1e-5 and res["f32"]["e_u"] <= 1e-5
-    assert res["f32"]["e_wss"] <= 1e-3
-    assert res["f16"]["e_rho"] <= 1e-2 and res["f16"]["e_u"] <= 0.2
+    check_bars(res["f32"], BARS[case]["f32"], f"{case} f32")
+    check_bars(res["f16"], BARS[case]["f16"], f"{case} f16")

@@ -9,7 +9,7 @@ import pytest
 import oracle
 from paper_2202_11770_amd import geometry as G
 from paper_2202_11770_amd import hlb
-from _parity import errors, fmt
+from _parity import check_bars, errors, fmt
 
 pytestmark = pytest.mark.gpu
 
@@ -73,8 +73,8 @@ def test_push_reduced_precision():
         (rho, u, wss), m, r = _run(g, tau, steps, st, "push", tables)
         res[st] = errors(rho, u, wss, *ref)
         print(f"push {st}: {fmt(res[st])} mass residual {r / m:.2e}", flush=True)
-    assert res["f32"]["e_rho"] <= 1e-5 and res["f32"]["e_u"] <= 1e-5 and res["f32"]["e_wss"] <= 1e-3
-    assert res["f16"]["e_rho"] <= 1e-2 and res["f16"]["e_u"] <= 0.2
+    check_bars(res["f32"], dict(e_rho=3e-7, e_u=1e-5, e_wss=2e-5), "push f32")
+    check_bars(res["f16"], dict(e_rho=3e-5, e_u=2e-3, e_wss=5e-3), "push f16")
 
 
 def test_push_state_exchange():

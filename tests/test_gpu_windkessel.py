@@ -6,7 +6,7 @@ import pytest
 import oracle
 from paper_2202_11770_amd import geometry as G
 from paper_2202_11770_amd import hlb
-from _parity import errors, fmt
+from _parity import check_bars, errors, fmt
 
 pytestmark = pytest.mark.gpu
 
@@ -67,7 +67,7 @@ def test_windkessel_fp32_and_errors():
     sim.step(steps)
     e = errors(*sim.macros(), *ref)
     print(f"tree f32 Windkessel: {fmt(e)}", flush=True)
-    assert e["e_rho"] <= 1e-5 and e["e_u"] <= 1e-5
+    check_bars(e, dict(e_rho=2e-7, e_u=5e-6, e_wss=1e-5), "Windkessel f32")
     k_vel = [k for k, io in enumerate(g.iolets) if io.kind == G.VELOCITY][0]
     k_out = next(iter(models))
     with pytest.raises(hlb.HLBError, match="not a pressure iolet"):

@@ -64,7 +64,7 @@ def _J(orc, d, tables=None, phi=None):
 
 def test_objective_matches_forward(orc, adj):
     assert adj["J"] != 0
-    assert abs(_J(orc, adj) - adj["J"]) <= 1e-13 * abs(adj["J"])
+    assert abs(_J(orc, adj) - adj["J"]) <= 1e-14 * abs(adj["J"])
 
 
 def _table_fd(orc, d, kind, h):
