@@ -246,6 +246,22 @@ hlb_status hlb_set_state(hlb_ctx *ctx, const double *f, int64_t t);
  * not finite. */
 hlb_status hlb_mass_balance(hlb_ctx *ctx, double *mass, double *residual);
 
+/* hlb_mass_balance for callers that cannot allocate device memory or wait
+ * on the host (code under HIP graph capture, tight serving loops): writes
+ * out[0] = M(t) and out[1] = R(t), bit for bit the values hlb_mass_balance
+ * returns, to `out`, caller-owned device memory of 2 doubles, asynchronously
+ * on the context stream.  It calls no hipMalloc / hipFree and does not
+ * synchronise; the non-finite check of hlb_mass_balance is left to the
+ * caller.  The reduction's partial sums go to a fixed array of 8,192
+ * doubles (64 KiB) in device memory that every GPU the library runs on
+ * holds until the process ends; each call overwrites the slots it reads, so
+ * nothing is cleared between calls, and any site count is served (larger
+ * states stride over the slots).  All calls on one GPU share that array:
+ * calls that may overlap on one GPU (two streams, two threads) race and
+ * must be ordered by the caller.  Errors: HLB_EINVAL (null ctx or out),
+ * HLB_EDEVICE. */
+hlb_status hlb_mass_balance_noalloc(hlb_ctx *ctx, void *out);
+
 /* Current time step t. */
 hlb_status hlb_time(const hlb_ctx *ctx, int64_t *t);
 

@@ -21,6 +21,7 @@
 #include "hlb_adjoint.h"
 #include "hlb_aux.h"
 #include "hlb_internal.h"
+#include "hlb_noalloc.h"
 
 using namespace hlb;
 
@@ -719,6 +720,13 @@ static hlb_status create_impl(int64_t n, const int32_t *coords, const uint8_t *t
     delete c;
     return fail(HLB_EDEVICE, "no HIP device: %s", hipGetErrorString(he));
   }
+  // device address of the allocation-free reduction's partial sums, looked
+  // up once per device here so that hlb_mass_balance_noalloc never has to
+  if ((he = noalloc_setup(nullptr)) != hipSuccess) {
+    (void)hipGetLastError();
+    delete c;
+    return fail(HLB_EDEVICE, "hipGetSymbolAddress of the reduction scratch: %s", hipGetErrorString(he));
+  }
   const size_t fb = (size_t)Q * np * storage_bytes(opt.storage);
   const int64_t partial_len = 1 + 8192;
   const size_t need = 2 * fb + pull_io.size() * sizeof(int32_t) + seg_off.size() * sizeof(int32_t) +
@@ -1301,6 +1309,15 @@ hlb_status hlb_set_state(hlb_ctx *c, const double *f, int64_t t) {
   c->direct = true;
   c->t = t;
   return reset_balance(c);
+}
+
+hlb_status hlb_mass_balance_noalloc(hlb_ctx *c, void *out) {
+  if (hlb_status st = check_ctx(c)) return st;
+  if (!out) return fail(HLB_EINVAL, "out is null");
+  if (hlb_status st = bind(c)) return st;
+  HIP_TRY(launch_mass_balance_noalloc(c->cfg, c->L, c->d, c->cur, mass_offset(c), c->m0, static_cast<double *>(out),
+                                      c->stream));
+  return HLB_OK;
 }
 
 hlb_status hlb_mass_balance(hlb_ctx *c, double *mass, double *residual) {

@@ -95,6 +95,7 @@ _SIGS = {
     "hlb_get_state": [_P, _P],
     "hlb_set_state": [_P, _P, _i64],
     "hlb_mass_balance": [_P, _P, _P],
+    "hlb_mass_balance_noalloc": [_P, _P],
     "hlb_time": [_P, ctypes.POINTER(_i64)],
     "hlb_info": [_P, ctypes.POINTER(hlb_info_t)],
     "hlb_set_timing": [_P, _i32],
@@ -375,6 +376,13 @@ def hlb_time(ctx) -> int:
     t = ctypes.c_int64()
     _check(load().hlb_time(ctx, ctypes.byref(t)), "hlb_time")
     return t.value
+
+
+def hlb_mass_balance_noalloc(ctx, out):
+    """out: a contiguous float64 CUDA tensor of 2 elements, caller-allocated;
+    receives (M(t), R(t)) asynchronously on the context stream.  Nothing is
+    allocated by this call or by the library."""
+    _check(load().hlb_mass_balance_noalloc(ctx, _dev_f64(out, 2, "out")), "hlb_mass_balance_noalloc")
 
 
 def hlb_set_timing(ctx, enable: bool):

@@ -151,5 +151,6 @@ def test_null_arguments():
     assert lib.hlb_time(None, None) == hlb.HLB_EINVAL
     assert lib.hlb_set_objective(None, 0, None) == hlb.HLB_EINVAL
     assert lib.hlb_set_porosity_device(None, None) == hlb.HLB_EINVAL
+    assert lib.hlb_mass_balance_noalloc(None, None) == hlb.HLB_EINVAL
     assert lib.hlb_set_iolet_table_device(None, 0, None, 1) == hlb.HLB_EINVAL
     assert lib.hlb_adjoint_run_device(None, 1, 0, 1, 1, None, None, None, None) == hlb.HLB_EINVAL
