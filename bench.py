@@ -210,24 +210,25 @@ def compare_storages(g, tables, tau, storages, steps):
     return out
 
 
-def run_split(g, tables, tau, storage, steps, warmup, nparts):
+def run_split(g, tables, tau, storage, steps, warmup, nparts, exchange="direct"):
     """The same workload as nparts partitions on this GPU with the halo
     exchange overlapped (the one-GPU emulation of a domain split)."""
     import torch
     from paper_2202_11770_amd import halo
     t0 = time.time()
-    sp = halo.SplitSimulation(g, tau, storage=storage, tables=tables, nparts=nparts)
-    log(f"split {storage}: {nparts} parts created in {time.time() - t0:.1f}s")
+    sp = halo.SplitSimulation(g, tau, storage=storage, tables=tables, nparts=nparts, exchange=exchange)
+    log(f"split {storage} ({exchange} exchange): {nparts} parts created in {time.time() - t0:.1f}s")
     sp.step(warmup)
     sp.synchronize()
     t0 = time.perf_counter()
     sp.step(steps)
     sp.synchronize()
     dt = time.perf_counter() - t0
-    n_halo = sum(int(b.numel()) for b in sp.send)
+    n_halo = sum(int(v[0].size) for P in sp.parts for v in P.send.values())
     ghosts = sum(P.glob.size - P.n_owned for P in sp.parts)
     sp.close()
-    return {"parts": nparts, "mlups": round(g.n * steps / dt / 1e6, 1), "ms_per_step": round(dt / steps * 1e3, 4),
+    return {"parts": nparts, "exchange": exchange, "mlups": round(g.n * steps / dt / 1e6, 1),
+            "ms_per_step": round(dt / steps * 1e3, 4),
             "halo_values_per_step": n_halo, "ghost_sites": int(ghosts)}
 
 
@@ -298,8 +299,10 @@ def oracle_table(g20, tables20, budget_s=4.0):
 
 def run_adjoint(g, tables, tau, n=40, n_snap=10):
     """hlb_adjoint_run on the workload (FP64, WSS objective over the last
-    half of n steps): the reverse step's kernels timed with HIP events and
-    set against their algorithmic bytes per site:
+    half of n steps; also timed with every step inside the window and with
+    none, and the mean for the differentiation protocol's window, the last
+    sixth of the steps): the reverse step's kernels timed with HIP events
+    and set against their algorithmic bytes per site:
       k_adj_collide: gather of s (19 x 8 + the pull table), mu read, nu
                      written (19 x 8 each), porosity derivative read and
                      written (16), order (4);
@@ -309,22 +312,36 @@ def run_adjoint(g, tables, tau, n=40, n_snap=10):
     from paper_2202_11770_amd import hlb
     sim = hlb.Simulation.create(g, tau, tables=tables, adjoint=True)
     info = sim.info()
-    hlb.hlb_set_timing(sim.ctx, True)
-    t0 = time.perf_counter()
-    J, _, _, fw = hlb.hlb_adjoint_run(sim.ctx, n, n // 2, n, n_snap)
-    wall = time.perf_counter() - t0
-    st = hlb.hlb_stats(sim.ctx)
+
+    def timed(w0, w1):
+        hlb.hlb_set_timing(sim.ctx, True)
+        t0 = time.perf_counter()
+        J, _, _, fw = hlb.hlb_adjoint_run(sim.ctx, n, w0, w1, n_snap)
+        wall = time.perf_counter() - t0
+        return J, fw, wall, hlb.hlb_stats(sim.ctx)["adj_ms"]
+
+    J, fw, wall, adj_ms = timed(n // 2, n)
+    # reverse steps inside the objective window (the boundary kernel also
+    # takes every wall site) and outside it (iolet sites only)
+    in_ms = timed(0, n)[3]
+    out_ms = timed(n, n)[3]
     # the forward step kernel in the same context (its site order)
     hlb.hlb_set_timing(sim.ctx, True)
     sim.step(20)
     fwd_ms = hlb.hlb_stats(sim.ctx)["kernel_ms"]
     sim.close()
     bps = 5 * 19 * 8 + 2 * info["table_bytes_per_site"] + 16 + 4 + 4
-    gbs = bps * info["n_sites"] / (st["adj_ms"] * 1e-3) / 1e9
-    return {"steps": n, "snapshots": n_snap, "forward_steps": fw, "wall_s": round(wall, 3),
-            "reverse_step_ms": round(st["adj_ms"], 4), "bytes_per_site": round(bps, 2),
-            "achieved_gbs": round(gbs, 1), "frac": round(gbs / PEAK_GBS, 4),
-            "reverse_mlups": round(info["n_sites"] / st["adj_ms"] / 1e3, 1),
+    gbs = lambda ms: bps * info["n_sites"] / (ms * 1e-3) / 1e9
+    c4_ms = (500 * in_ms + 2500 * out_ms) / 3000  # the protocol's window: the last 500 of 3000 steps
+    return {"steps": n, "snapshots": n_snap, "window": [n // 2, n], "forward_steps": fw, "wall_s": round(wall, 3),
+            "reverse_step_ms": round(adj_ms, 4), "bytes_per_site": round(bps, 2),
+            "achieved_gbs": round(gbs(adj_ms), 1), "frac": round(gbs(adj_ms) / PEAK_GBS, 4),
+            "reverse_mlups": round(info["n_sites"] / adj_ms / 1e3, 1),
+            "reverse_step_in_window_ms": round(in_ms, 4), "frac_in_window": round(gbs(in_ms) / PEAK_GBS, 4),
+            "reverse_step_outside_window_ms": round(out_ms, 4),
+            "frac_outside_window": round(gbs(out_ms) / PEAK_GBS, 4),
+            "reverse_step_ms_window_last_sixth": round(c4_ms, 4),
+            "frac_window_last_sixth": round(gbs(c4_ms) / PEAK_GBS, 4),
             "forward_step_ms": round(fwd_ms, 4), "J": J}
 
 
@@ -519,9 +536,12 @@ def main():
     split = {}
     if args.split > 1:
         for st in args.storages.split(","):
-            split[st] = run_split(g, tables, tau, st, args.steps, args.warmup, args.split)
-            split[st]["overhead_vs_single"] = round(results[st]["mlups"] / split[st]["mlups"] - 1.0, 4)
-            log(f"split {st}: {split[st]}")
+            split[st] = {}
+            for ex in ("direct", "copy"):
+                r = run_split(g, tables, tau, st, args.steps, args.warmup, args.split, exchange=ex)
+                r["overhead_vs_single"] = round(results[st]["mlups"] / r["mlups"] - 1.0, 4)
+                split[st][ex] = r
+                log(f"split {st}: {r}")
     compare = None
     if args.compare_steps > 0:
         compare = compare_storages(g, tables, tau, args.storages.split(","), args.compare_steps)

@@ -366,6 +366,34 @@ hlb_status hlb_halo_set(hlb_ctx *ctx, int64_t n_send, const int32_t *send_site, 
  * receive buffer into the current state's ghost slots (context stream). */
 hlb_status hlb_halo_pack(hlb_ctx *ctx);
 hlb_status hlb_halo_unpack(hlb_ctx *ctx);
+/* Direct exchange (the design for more than one GPU: the receiver's ghost
+ * slots are written by the sender, no receive buffer and no unpack):
+ * hlb_halo_ghost_slots: for n (ghost site, direction) pairs of a partition
+ *   (host, caller ids), elem[k] (host, [n]) receives the element index of
+ *   that ghost slot in the partition's population buffers (the same in
+ *   both) and buf[0], buf[1] the two buffers' device addresses (fixed for
+ *   the context's life).  Errors: HLB_EINVAL (not a ghost site, direction
+ *   out of range, null output), HLB_ESTATE (not a partition).
+ * hlb_halo_add_peer: adds a peer to which this partition sends n values:
+ *   entry k is population dir[k] of edge site site[k] (host, caller ids),
+ *   written to element peer_elem[k] (host) of the peer's buffers
+ *   (peer_buf0, peer_buf1, device memory; from hlb_halo_ghost_slots, or
+ *   the same buffers mapped from another GPU).  hlb_step_edge then writes
+ *   the new values into the peer buffer with the index of the buffer it
+ *   writes itself, and hlb_halo_pack the current values into the peer
+ *   buffer with the index of its current one: the partitions must advance
+ *   in lockstep from a common start (equal buffer indices), and a
+ *   partition's hlb_step_edge must not start before its peers' previous
+ *   hlb_step_edge has finished (the last reader of the slots it writes and
+ *   the writer of those it reads); hlb_halo_unpack has nothing to do for
+ *   such a peer.  Errors: HLB_EINVAL (n < 1, not an edge site, direction
+ *   out of range, a negative element, null buffer), HLB_ESTATE.
+ * hlb_halo_clear_peers: removes every peer. */
+hlb_status hlb_halo_ghost_slots(hlb_ctx *ctx, int64_t n, const int32_t *site, const int32_t *dir, int64_t *elem,
+                                void **buf);
+hlb_status hlb_halo_add_peer(hlb_ctx *ctx, int64_t n, const int32_t *site, const int32_t *dir, void *peer_buf0,
+                             void *peer_buf1, const int64_t *peer_elem);
+hlb_status hlb_halo_clear_peers(hlb_ctx *ctx);
 /* One step t -> t+1 in two launches, so that the transfer of the edge
  * values overlaps the rest of the update:
  *   hlb_step_edge: the iolet groups and the edge blocks of the bulk+wall

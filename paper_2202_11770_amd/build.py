@@ -46,13 +46,16 @@ def build(verbose: bool = False, extra_hipcc=()) -> str:
     xobj = os.path.join(BUILD, "hlb_aux.o")
     _run([os.path.join(ROCM, "bin", "hipcc"), *HIPCC_FLAGS, *inc, "-c",
           os.path.join(CSRC, "hlb_aux.hip"), "-o", xobj], verbose)
+    hobj = os.path.join(BUILD, "hlb_halo.o")
+    _run([os.path.join(ROCM, "bin", "hipcc"), *HIPCC_FLAGS, *inc, "-c",
+          os.path.join(CSRC, "hlb_halo.hip"), "-o", hobj], verbose)
     nobj = os.path.join(BUILD, "hlb_noalloc.o")
     _run([os.path.join(ROCM, "bin", "hipcc"), *HIPCC_FLAGS, *inc, "-c",
           os.path.join(CSRC, "hlb_noalloc.hip"), "-o", nobj], verbose)
     _run(["g++", "-O2", "-std=c++17", "-fPIC", "-fopenmp", "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(ROCM, "include"),
           *inc, "-c", os.path.join(CSRC, "hlb_runtime.cpp"), "-o", robj], verbose)
     tmp = LIB + ".tmp"
-    _run(["g++", "-shared", "-fopenmp", kobj, cobj, aobj, xobj, nobj, robj, "-o", tmp, "-L", os.path.join(ROCM, "lib"),
+    _run(["g++", "-shared", "-fopenmp", kobj, cobj, aobj, xobj, hobj, nobj, robj, "-o", tmp, "-L", os.path.join(ROCM, "lib"),
           "-Wl,-rpath," + os.path.join(ROCM, "lib"), "-lamdhip64"], verbose)
     os.replace(tmp, LIB)
     return LIB

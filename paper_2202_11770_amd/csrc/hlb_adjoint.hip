@@ -13,7 +13,6 @@
 // (the site at x + c_i is the pull entry of direction opp(i)), so nothing is
 // scattered and no further table is needed.
 
-#include "hlb_adjoint.h"
 #include "hlb_device.h"
 
 namespace hlb {
@@ -36,8 +35,6 @@ struct AdjArgs {
   double *dphi;             // [np], accumulated over the sweep
   int objective;            // HLB_OBJ_WSS or HLB_OBJ_IOLET_FLUX
   const double *w;          // [n_io] iolet-flux weights
-  int wss_fused;            // the WSS objective's terms were added by k_adj_collide
-  double *jpart;            // [blocks of np]: per-workgroup objective sums of k_adj_collide_wss
 };
 
 // (dM/dg)^T w for M(g) = f^eq(rho(g), u(g)):
@@ -159,163 +156,6 @@ __global__ __launch_bounds__(kBlock) void k_adj_collide(AdjArgs A) {
   }
 }
 
-// k_adj_collide without porosity for the steps in the WSS objective's
-// window: the objective's terms at the sites with wall links are added here
-// too, so that k_adj_boundary does not reload nu and re-gather s_{t-1} at
-// those scattered sites.  WSS(g) = |s|, s the tangential part of the
-// traction fac P n (P the non-equilibrium second moment of g,
-// fac = -(1 - 1/(2 tau)), n the normalised sum of the wall-link directions
-// with the sign flipped); with e = s / |s|,
-//   d WSS / d(g - f^eq)_i = wd_i = fac (c_i.n)(c_i.e),
-//   d WSS / d g = wd - (dM/dg)^T wd        (M(g) = f^eq(rho(g), u(g))),
-// which is added to nu before it is stored; its share of the porosity
-// derivative at zero porosity, the sum over wall links of inc_j h_j, is
-//   fac/|s| n^T H2 s - wa H - wb.(Hc - u H),  H2 = sum h_j c_j c_j^T,
-// with (wa, wb) = (dM/dg)^T wd as in eq_transpose.
-// Registers: g lives only until its moments (density, momentum, second
-// moment) and the wall sums are formed.  mu is then read twice, one value
-// at a time: a first pass forms the sums of eq_transpose (and sum mu_j h_j,
-// with h_j read again from the site's own slot), a second pass, from cache,
-// the output nu_j.  Holding the 19 values of mu (or of wd) across the
-// objective's terms took 256 VGPRs and spilled.  The site's WSS goes to the
-// workgroup's slot of jpart (no atomics; summed after the sweep).
-__global__ __launch_bounds__(kBlock) void k_adj_collide_wss(AdjArgs A) {
-  const GatherArgs &a = A.a;
-  const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  double jw = 0.0;
-  if (p < a.np && A.order[p] >= 0) {
-    const int32_t p32 = (int32_t)p;
-    uint32_t wall, iol;
-    link_masks(a, p, wall, iol);
-    double rho, ux, uy, uz;
-    double pxx = 0, pyy = 0, pzz = 0, pxy = 0, pxz = 0, pyz = 0;  // second moment of g, then P
-    double h0 = 0, hx = 0, hy = 0, hz = 0;
-    double qxx = 0, qyy = 0, qzz = 0, qxy = 0, qxz = 0, qyz = 0;  // H2
-    {
-      double g[Q];
-      if (p < a.io_begin)
-        gather<false, false, false>(A.S, p, p / kBlock, a, g);
-      else
-        gather<true, false, false>(A.S, p, 0, a, g);
-      double dr, jx, jy, jz;
-      moments<false>(g, 0.0, dr, rho, jx, jy, jz);
-      ux = jx / rho;
-      uy = jy / rho;
-      uz = jz / rho;
-#pragma unroll
-      for (int i = 1; i < Q; ++i) {
-        if (cx(i)) pxx += g[i];
-        if (cy(i)) pyy += g[i];
-        if (cz(i)) pzz += g[i];
-        if (cx(i) && cy(i)) pxy += cx(i) * cy(i) > 0 ? g[i] : -g[i];
-        if (cx(i) && cz(i)) pxz += cx(i) * cz(i) > 0 ? g[i] : -g[i];
-        if (cy(i) && cz(i)) pyz += cy(i) * cz(i) > 0 ? g[i] : -g[i];
-        const double h = ((wall >> (i - 1)) & 1u) ? wgt<double>(i) * a.rho0 - g[i] : 0.0;
-        h0 += h;
-        hx += h * cx(i);
-        hy += h * cy(i);
-        hz += h * cz(i);
-        qxx += h * (cx(i) * cx(i));
-        qyy += h * (cy(i) * cy(i));
-        qzz += h * (cz(i) * cz(i));
-        qxy += h * (cx(i) * cy(i));
-        qxz += h * (cx(i) * cz(i));
-        qyz += h * (cy(i) * cz(i));
-      }
-      // sum f^eq c c = rho/3 I + rho u u (eq. (4) with the 1/2 factors)
-      pxx -= rho * (1.0 / 3.0 + ux * ux);
-      pyy -= rho * (1.0 / 3.0 + uy * uy);
-      pzz -= rho * (1.0 / 3.0 + uz * uz);
-      pxy -= rho * ux * uy;
-      pxz -= rho * ux * uz;
-      pyz -= rho * uy * uz;
-    }
-    // the objective's terms: e, n scaled, and (wa, wb); zero where the site
-    // has no wall link or no tangential traction
-    double nx = 0, ny = 0, nz = 0, sx = 0, sy = 0, sz = 0, fw = 0.0;
-    double wa = 0.0, wbx = 0.0, wby = 0.0, wbz = 0.0, dphi_w = 0.0;
-    if (wall) {
-#pragma unroll
-      for (int i = 1; i < Q; ++i)
-        if (wall & (1u << (i - 1))) {
-          nx -= cx(i);
-          ny -= cy(i);
-          nz -= cz(i);
-        }
-      const double nn = sqrt(nx * nx + ny * ny + nz * nz);
-      const double inn = nn > 0.0 ? 1.0 / nn : 0.0;  // no normal: no stress term
-      nx *= inn;
-      ny *= inn;
-      nz *= inn;
-      const double fac = -(1.0 - 1.0 / (2.0 * A.tau));
-      const double tx = fac * (pxx * nx + pxy * ny + pxz * nz);
-      const double ty = fac * (pxy * nx + pyy * ny + pyz * nz);
-      const double tz = fac * (pxz * nx + pyz * ny + pzz * nz);
-      const double tn = tx * nx + ty * ny + tz * nz;
-      sx = tx - tn * nx;
-      sy = ty - tn * ny;
-      sz = tz - tn * nz;
-      const double w = sqrt(sx * sx + sy * sy + sz * sz);
-      if (w > 0.0) {
-        jw = w;
-        fw = fac / w;
-        const double usq = 1.5 * (ux * ux + uy * uy + uz * uz);
-#pragma unroll
-        for (int i = 0; i < Q; ++i) {
-          const double cu = cx(i) * ux + cy(i) * uy + cz(i) * uz;
-          const double v = fw * (cx(i) * nx + cy(i) * ny + cz(i) * nz) * (cx(i) * sx + cy(i) * sy + cz(i) * sz);
-          wa += v * (wgt<double>(i) * (1.0 + 3.0 * cu + 4.5 * cu * cu - usq));
-          const double sv = v * wgt<double>(i);
-          wbx += sv * (3.0 * cx(i) + 9.0 * cu * cx(i) - 3.0 * ux);
-          wby += sv * (3.0 * cy(i) + 9.0 * cu * cy(i) - 3.0 * uy);
-          wbz += sv * (3.0 * cz(i) + 9.0 * cu * cz(i) - 3.0 * uz);
-        }
-        const double q_ns = nx * (qxx * sx + qxy * sy + qxz * sz) + ny * (qxy * sx + qyy * sy + qyz * sz) +
-                            nz * (qxz * sx + qyz * sy + qzz * sz);
-        dphi_w = fw * q_ns - wa * h0 - (wbx * (hx - ux * h0) + wby * (hy - uy * h0) + wbz * (hz - uz * h0));
-      }
-    }
-    // first pass over mu: the sums of eq_transpose and sum mu_j h_j
-    double ea = 0.0, ebx = 0.0, eby = 0.0, ebz = 0.0, hm = 0.0;
-    {
-      const double usq = 1.5 * (ux * ux + uy * uy + uz * uz);
-#pragma unroll
-      for (int i = 0; i < Q; ++i) {
-        const double mi = A.mu[pidx(p32, i)];
-        const double cu = cx(i) * ux + cy(i) * uy + cz(i) * uz;
-        ea += mi * (wgt<double>(i) * (1.0 + 3.0 * cu + 4.5 * cu * cu - usq));
-        const double sv = mi * wgt<double>(i);
-        ebx += sv * (3.0 * cx(i) + 9.0 * cu * cx(i) - 3.0 * ux);
-        eby += sv * (3.0 * cy(i) + 9.0 * cu * cy(i) - 3.0 * uy);
-        ebz += sv * (3.0 * cz(i) + 9.0 * cu * cz(i) - 3.0 * uz);
-        if (i > 0 && ((wall >> (i - 1)) & 1u)) hm += mi * (wgt<double>(i) * a.rho0 - A.S[pidx(p32, opp(i))]);
-      }
-    }
-    // read mu again below instead of holding it (the loads above are not reused)
-    asm volatile("" ::: "memory");
-#pragma unroll
-    for (int j = 0; j < Q; ++j) {
-      const double mj = A.mu[pidx(p32, j)];
-      const double wdj = fw * (cx(j) * nx + cy(j) * ny + cz(j) * nz) * (cx(j) * sx + cy(j) * sy + cz(j) * sz);
-      const double v = (1.0 - A.omega) * mj + A.omega * (ea + ebx * (cx(j) - ux) + eby * (cy(j) - uy) + ebz * (cz(j) - uz)) +
-                       (wdj - (wa + wbx * (cx(j) - ux) + wby * (cy(j) - uy) + wbz * (cz(j) - uz)));
-      __builtin_nontemporal_store(v, &A.nu[pidx(p32, j)]);
-    }
-    if (wall)
-      A.dphi[p] += (1.0 - A.omega) * hm +
-                   A.omega * (ea * h0 + ebx * (hx - ux * h0) + eby * (hy - uy * h0) + ebz * (hz - uz * h0)) + dphi_w;
-  }
-  __shared__ double red[kBlock / 64];
-  const double sw = wave_sum(jw);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = sw;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double b = 0.0;
-    for (int k = 0; k < kBlock / 64; ++k) b += red[k];
-    if (b != 0.0) A.jpart[blockIdx.x] += b;
-  }
-}
-
 // The rest of nu_t and the parameter derivatives of the update t-1 -> t, at
 // the sites with wall or iolet links (list, ascending positions):
 //   WSS objective (in the window): + dWSS(g_t)/dg_t, J += WSS;
@@ -335,7 +175,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) 
   if (k_site < n_list) {
     const int64_t p = list[k_site];
     const int32_t p32 = (int32_t)p;
-    const bool wss_on = A.objective == HLB_OBJ_WSS && A.in_window && !A.wss_fused;
+    const bool wss_on = A.objective == HLB_OBJ_WSS && A.in_window;
     uint32_t wall, iol;
     link_masks(a, p, wall, iol);
     // WSS of g_t and what its gradient needs (scalars), before nu is loaded
@@ -354,17 +194,23 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) 
         ux = jx / rho;
         uy = jy / rho;
         uz = jz / rho;
-        const double usq = 1.5 * (ux * ux + uy * uy + uz * uz);
+        // P = sum g c c - sum f^eq c c, with sum f^eq c c = rho/3 I + rho u u
+        // (eq. (4) with the 1/2 factors): no equilibrium is evaluated
 #pragma unroll
-        for (int i = 0; i < Q; ++i) {
-          const double d = g[i] - s_eq<false>(i, 0.0, rho, ux, uy, uz, usq);
-          pxx += d * cx(i) * cx(i);
-          pyy += d * cy(i) * cy(i);
-          pzz += d * cz(i) * cz(i);
-          pxy += d * cx(i) * cy(i);
-          pxz += d * cx(i) * cz(i);
-          pyz += d * cy(i) * cz(i);
+        for (int i = 1; i < Q; ++i) {
+          if (cx(i)) pxx += g[i];
+          if (cy(i)) pyy += g[i];
+          if (cz(i)) pzz += g[i];
+          if (cx(i) && cy(i)) pxy += cx(i) * cy(i) > 0 ? g[i] : -g[i];
+          if (cx(i) && cz(i)) pxz += cx(i) * cz(i) > 0 ? g[i] : -g[i];
+          if (cy(i) && cz(i)) pyz += cy(i) * cz(i) > 0 ? g[i] : -g[i];
         }
+        pxx -= rho * (1.0 / 3.0 + ux * ux);
+        pyy -= rho * (1.0 / 3.0 + uy * uy);
+        pzz -= rho * (1.0 / 3.0 + uz * uz);
+        pxy -= rho * ux * uy;
+        pxz -= rho * ux * uz;
+        pyz -= rho * uy * uz;
       }
 #pragma unroll
       for (int i = 1; i < Q; ++i)
@@ -409,16 +255,21 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) 
     // collision's part is added by k_adj_collide)
     double dphi = 0.0;
     if (w > 0.0) {
-      // dWSS/d(g - f^eq)_i = fac (c_i.n)(e.c_i), e = s/|s|; then through f^eq(g)
-      double wd[Q];
-#pragma unroll
-      for (int i = 0; i < Q; ++i)
-        wd[i] = fac * (cx(i) * nx + cy(i) * ny + cz(i) * nz) * (cx(i) * sx + cy(i) * sy + cz(i) * sz) / w;
-      double wa, wbx, wby, wbz;
-      eq_transpose(wd, rho, ux, uy, uz, wa, wbx, wby, wbz);
+      // dWSS/d(g - f^eq)_i = wd_i = fac (c_i.n)(e.c_i), e = s/|s|; then
+      // through f^eq(g): (wa, wb) = eq_transpose(wd) in closed form, since
+      // wd_i = fw c_i.N c_i with N = n s^T, fw = fac/|s|, and the lattice
+      // sums sum w c c = I/3, sum w c c c = 0, sum w c c c c = (1/9)(the
+      // three pairings of deltas) give
+      //   wa = fw ((n.s)/3 + (u.n)(u.s)),  wb = fw (n (s.u) + s (n.u)),
+      // with n.s = 0 (s is tangential)
+      const double fw = fac / w;
+      const double un = ux * nx + uy * ny + uz * nz, us = ux * sx + uy * sy + uz * sz;
+      const double wa = fw * un * us;
+      const double wbx = fw * (nx * us + sx * un), wby = fw * (ny * us + sy * un), wbz = fw * (nz * us + sz * un);
 #pragma unroll
       for (int j = 0; j < Q; ++j) {
-        const double inc = wd[j] - (wa + wbx * (cx(j) - ux) + wby * (cy(j) - uy) + wbz * (cz(j) - uz));
+        const double wdj = fw * (cx(j) * nx + cy(j) * ny + cz(j) * nz) * (cx(j) * sx + cy(j) * sy + cz(j) * sz);
+        const double inc = wdj - (wa + wbx * (cx(j) - ux) + wby * (cy(j) - uy) + wbz * (cz(j) - uz));
         m[j] += inc;
         if (!POROUS && j > 0 && (wall & (1u << (j - 1))))
           dphi += inc * (wgt<double>(j) * a.rho0 - A.S[pidx(p32, opp(j))]);
@@ -595,8 +446,6 @@ hipError_t launch_adjoint_step(const LaunchCfg &cfg, const Layout &L, const DevP
   A.dphi = b.dphi;
   A.objective = b.objective;
   A.w = b.w;
-  A.wss_fused = 0;
-  A.jpart = b.J + kAdjJPart;
   const unsigned grid = blocks_of(L.np);
   if (cfg.porous) {
     k_adj_collide<true><<<grid, kBlock, 0, s>>>(A);
@@ -604,42 +453,17 @@ hipError_t launch_adjoint_step(const LaunchCfg &cfg, const Layout &L, const DevP
       k_adj_boundary<true><<<blocks_of(b.n_blist), kBlock, 0, s>>>(A, b.blist, b.n_blist);
     k_adj_stream<true><<<grid, kBlock, 0, s>>>(A);
   } else {
-    // without porosity the collide kernel takes the WSS objective's terms
-    // too (in the window), and only the sites with iolet links (the list's
-    // tail) have terms left for the boundary kernel
-    if (b.objective == HLB_OBJ_WSS && in_window) {
-      A.wss_fused = 1;
-      k_adj_collide_wss<<<grid, kBlock, 0, s>>>(A);
-    } else {
-      k_adj_collide<false><<<grid, kBlock, 0, s>>>(A);
-    }
-    const int64_t n_list = b.n_blist - b.n_blist_wall;
-    if (n_list > 0) k_adj_boundary<false><<<blocks_of(n_list), kBlock, 0, s>>>(A, b.blist + b.n_blist_wall, n_list);
+    k_adj_collide<false><<<grid, kBlock, 0, s>>>(A);
+    // without porosity and outside the WSS objective's window only the
+    // sites with iolet links (the list's tail) have terms left
+    const bool walls_too = b.objective == HLB_OBJ_WSS && in_window;
+    const int32_t *list = walls_too ? b.blist : b.blist + b.n_blist_wall;
+    const int64_t n_list = walls_too ? b.n_blist : b.n_blist - b.n_blist_wall;
+    if (n_list > 0) k_adj_boundary<false><<<blocks_of(n_list), kBlock, 0, s>>>(A, list, n_list);
     k_adj_stream<false><<<grid, kBlock, 0, s>>>(A);
   }
   return hipGetLastError();
 }
 
-namespace {
-// J[0] += sum of jpart[0..n) (one workgroup, fixed order).
-__global__ __launch_bounds__(kBlock) void k_adj_finish(const double *jpart, int64_t n, double *J) {
-  __shared__ double red[kBlock / 64];
-  double s = 0.0;
-  for (int64_t k = threadIdx.x; k < n; k += kBlock) s += jpart[k];
-  s = wave_sum(s);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double b = 0.0;
-    for (int w = 0; w < kBlock / 64; ++w) b += red[w];
-    J[0] += b;
-  }
-}
-}  // namespace
-
-hipError_t launch_adjoint_finish(const AdjBuffers &b, int64_t np, hipStream_t s) {
-  k_adj_finish<<<1, kBlock, 0, s>>>(b.J + kAdjJPart, adj_jpart_slots(np), b.J);
-  return hipGetLastError();
-}
 
 }  // namespace hlb

@@ -18,8 +18,8 @@
 #include <vector>
 
 #include "hlb.h"
-#include "hlb_adjoint.h"
 #include "hlb_aux.h"
+#include "hlb_halo.h"
 #include "hlb_internal.h"
 #include "hlb_noalloc.h"
 
@@ -169,6 +169,16 @@ struct hlb_ctx {
     bool defined = false;
     int64_t bytes = 0;
   } halo;
+  // direct exchange (hlb_halo_add_peer): values written straight into peer
+  // partitions' ghost slots
+  struct Peer {
+    int32_t *pos = nullptr, *dir = nullptr;  // this partition's positions and directions
+    int64_t *elem = nullptr;                 // the peer's element indices
+    int64_t n = 0;
+    void *buf[2] = {nullptr, nullptr};       // the peer's population buffers
+    int64_t bytes = 0;
+  };
+  std::vector<Peer> peers;
   bool split_pending = false;  // hlb_step_edge done, hlb_step_mid due
   bool adj_on = false;         // opt.adjoint at creation
   // Windkessel outlets (hlb_set_windkessel)
@@ -250,8 +260,19 @@ void free_halo(hlb_ctx *c) {
   c->halo = hlb_ctx::Halo();
 }
 
+void free_peers(hlb_ctx *c) {
+  for (auto &q : c->peers) {
+    if (q.pos) (void)hipFree(q.pos);
+    if (q.dir) (void)hipFree(q.dir);
+    if (q.elem) (void)hipFree(q.elem);
+    c->dev_bytes -= q.bytes;
+  }
+  c->peers.clear();
+}
+
 void free_all(hlb_ctx *c) {
   free_halo(c);
+  free_peers(c);
   auto F = [](void *p) { if (p) (void)hipFree(p); };
   F(c->d.f[0]); F(c->d.f[1]); F(c->d.nbr_io); F(c->d.seg_off); F(c->d.seg_base); F(c->d.seg_delta); F(c->d.order); F(c->d.corr); F(c->d.io); F(c->d.tables);
   F(c->d.phi); F(c->d.acc); F(c->d.partial); F(c->d.io_scratch);
@@ -590,7 +611,10 @@ static hlb_status create_impl(int64_t n, const int32_t *coords, const uint8_t *t
     pos = (pos + kGroupAlign - 1) / kGroupAlign * kGroupAlign;
   }
   L.gbeg[kGroups] = pos;
-  // ghost positions follow the groups, in caller order
+  // ghost positions follow the groups, in caller order, from a tile of
+  // their own: peers may write them while this partition's kernels write
+  // the owned positions, so no cache line holds both
+  if (n_ghost > 0) pos = (pos + kPopTile - 1) / kPopTile * kPopTile;
   L.ghost_begin = pos;
   L.n_ghost = n_ghost;
   pos += n_ghost;
@@ -1041,11 +1065,97 @@ hlb_status hlb_halo_set(hlb_ctx *c, int64_t n_send, const int32_t *send_site, co
 
 hlb_status hlb_halo_pack(hlb_ctx *c) {
   if (hlb_status st = check_ctx(c)) return st;
-  if (!c->halo.defined) return fail(HLB_ESTATE, "no halo lists (hlb_halo_set)");
+  if (!c->halo.defined && c->peers.empty()) return fail(HLB_ESTATE, "no halo lists (hlb_halo_set / hlb_halo_add_peer)");
   if (c->split_pending) return fail(HLB_ESTATE, "a split step is in progress");
   if (hlb_status st = bind(c)) return st;
-  HIP_TRY(launch_halo(c->cfg, c->d, c->cur, c->halo.send_pos, c->halo.send_dir, c->halo.n_send, c->halo.send_buf,
-                      true, c->stream));
+  if (c->halo.defined)
+    HIP_TRY(launch_halo(c->cfg, c->d, c->cur, c->halo.send_pos, c->halo.send_dir, c->halo.n_send, c->halo.send_buf,
+                        true, c->stream));
+  // the current state into the peers' current buffers
+  for (const auto &q : c->peers)
+    HIP_TRY(launch_pack_to_peer(c->cfg.storage, c->d.f[c->cur], q.pos, q.dir, q.n, q.buf[c->cur], q.elem, c->stream));
+  return HLB_OK;
+}
+
+hlb_status hlb_halo_ghost_slots(hlb_ctx *c, int64_t n, const int32_t *site, const int32_t *dir, int64_t *elem,
+                                void **buf) {
+  if (hlb_status st = check_ctx(c)) return st;
+  if (c->role_host.empty()) return fail(HLB_ESTATE, "not a partition (hlb_create_part)");
+  if (n < 0 || (n > 0 && (!site || !dir || !elem)) || !buf) return fail(HLB_EINVAL, "bad ghost list or outputs");
+  const int64_t ns = c->L.n_sites;
+  for (int64_t k = 0; k < n; ++k) {
+    const int32_t x = site[k], i = dir[k];
+    if (x < 0 || x >= ns || c->role_host[x] != HLB_PART_GHOST || i < 0 || i >= Q)
+      return fail(HLB_EINVAL, "entry %lld: needs a ghost site and a direction in [0, 19)", (long long)k);
+  }
+  for (int64_t k = 0; k < n; ++k) {
+    // element index of (position q, direction i) in the tiled buffers
+    const int64_t q = c->inv_host[site[k]];
+    elem[k] = (((q >> kPopTileShift) * Q + dir[k]) << kPopTileShift) + (q & (kPopTile - 1));
+  }
+  buf[0] = c->d.f[0];
+  buf[1] = c->d.f[1];
+  return HLB_OK;
+}
+
+hlb_status hlb_halo_add_peer(hlb_ctx *c, int64_t n, const int32_t *site, const int32_t *dir, void *peer_buf0,
+                             void *peer_buf1, const int64_t *peer_elem) {
+  if (hlb_status st = check_ctx(c)) return st;
+  if (c->role_host.empty()) return fail(HLB_ESTATE, "not a partition (hlb_create_part)");
+  if (c->split_pending) return fail(HLB_ESTATE, "a split step is in progress");
+  if (n < 1 || !site || !dir || !peer_buf0 || !peer_buf1 || !peer_elem)
+    return fail(HLB_EINVAL, "bad peer list or buffers");
+  const int64_t ns = c->L.n_sites;
+  std::vector<int32_t> sp(n), sd(n);
+  for (int64_t k = 0; k < n; ++k) {
+    const int32_t x = site[k], i = dir[k];
+    if (x < 0 || x >= ns || c->role_host[x] != HLB_PART_EDGE || i < 0 || i >= Q)
+      return fail(HLB_EINVAL, "entry %lld: needs an edge site and a direction in [0, 19)", (long long)k);
+    if (peer_elem[k] < 0) return fail(HLB_EINVAL, "entry %lld: negative peer element", (long long)k);
+    sp[k] = c->inv_host[x];
+    sd[k] = i;
+  }
+  if (hlb_status st = bind(c)) return st;
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  hlb_ctx::Peer q;
+  q.n = n;
+  q.buf[0] = peer_buf0;
+  q.buf[1] = peer_buf1;
+  void *p = nullptr;
+  auto put = [&](void **dst, const void *src, size_t bytes) -> hlb_status {
+    if (hlb_status st = dev_alloc(c, dst, bytes)) return st;
+    q.bytes += (int64_t)bytes;
+    hipError_t e = hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return fail(HLB_EDEVICE, "hipMemcpy: %s", hipGetErrorString(e));
+    return HLB_OK;
+  };
+  hlb_status st = put(&p, sp.data(), n * sizeof(int32_t));
+  q.pos = static_cast<int32_t *>(p);
+  if (!st) {
+    st = put(&p, sd.data(), n * sizeof(int32_t));
+    q.dir = static_cast<int32_t *>(p);
+  }
+  if (!st) {
+    st = put(&p, peer_elem, n * sizeof(int64_t));
+    q.elem = static_cast<int64_t *>(p);
+  }
+  if (st) {
+    if (q.pos) (void)hipFree(q.pos);
+    if (q.dir) (void)hipFree(q.dir);
+    if (q.elem) (void)hipFree(q.elem);
+    c->dev_bytes -= q.bytes;
+    return st;
+  }
+  c->peers.push_back(q);
+  return HLB_OK;
+}
+
+hlb_status hlb_halo_clear_peers(hlb_ctx *c) {
+  if (hlb_status st = check_ctx(c)) return st;
+  if (c->split_pending) return fail(HLB_ESTATE, "a split step is in progress");
+  if (hlb_status st = bind(c)) return st;
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  free_peers(c);
   return HLB_OK;
 }
 
@@ -1061,13 +1171,19 @@ hlb_status hlb_halo_unpack(hlb_ctx *c) {
 
 hlb_status hlb_step_edge(hlb_ctx *c) {
   if (hlb_status st = check_ctx(c)) return st;
-  if (!c->halo.defined) return fail(HLB_ESTATE, "no halo lists (hlb_halo_set)");
+  if (!c->halo.defined && c->peers.empty()) return fail(HLB_ESTATE, "no halo lists (hlb_halo_set / hlb_halo_add_peer)");
   if (c->split_pending) return fail(HLB_ESTATE, "hlb_step_mid must follow hlb_step_edge");
   if (hlb_status st = bind(c)) return st;
   HIP_TRY(launch_step(c->cfg, c->L, c->d, c->cur, c->t, c->stream, nullptr, nullptr, 1));
-  // the edge sites' new post-collision values, from the buffer being written
-  HIP_TRY(launch_halo(c->cfg, c->d, 1 - c->cur, c->halo.send_pos, c->halo.send_dir, c->halo.n_send,
-                      c->halo.send_buf, true, c->stream));
+  // the edge sites' new post-collision values, from the buffer being
+  // written: into the send buffer, or straight into the peers' buffers of
+  // the same index (the one their next step pulls from)
+  if (c->halo.defined)
+    HIP_TRY(launch_halo(c->cfg, c->d, 1 - c->cur, c->halo.send_pos, c->halo.send_dir, c->halo.n_send,
+                        c->halo.send_buf, true, c->stream));
+  for (const auto &q : c->peers)
+    HIP_TRY(launch_pack_to_peer(c->cfg.storage, c->d.f[1 - c->cur], q.pos, q.dir, q.n, q.buf[1 - c->cur], q.elem,
+                                c->stream));
   c->split_pending = true;
   return HLB_OK;
 }
@@ -1703,9 +1819,8 @@ hlb_status adjoint_sweep(hlb_ctx *c, int64_t n, int64_t obj_t0, int64_t obj_t1, 
     c->adj.nu = static_cast<double *>(p);
     if (hlb_status st = dev_alloc(c, &p, (size_t)np * sizeof(double))) return st;
     c->adj.dphi = static_cast<double *>(p);
-    // [0] the objective; [1, 5) the caller's flux accumulators while the
-    // sweep runs; from kAdjJPart the collide kernel's per-workgroup sums
-    if (hlb_status st = dev_alloc(c, &p, (size_t)(kAdjJPart + adj_jpart_slots(np)) * sizeof(double))) return st;
+    // [0] the objective; [1, 5) the caller's flux accumulators while the sweep runs
+    if (hlb_status st = dev_alloc(c, &p, 8 * sizeof(double))) return st;
     c->adj.J = static_cast<double *>(p);
   }
   if (c->adj_dA_len < std::max<int64_t>(1, nio * n)) {
@@ -1733,7 +1848,6 @@ hlb_status adjoint_sweep(hlb_ctx *c, int64_t n, int64_t obj_t0, int64_t obj_t1, 
   HIP_TRY(launch_zero(c->adj.mu, (int64_t)Q * np, c->stream));
   HIP_TRY(launch_zero(c->adj.dphi, np, c->stream));
   HIP_TRY(launch_zero(c->adj.J, 1, c->stream));
-  HIP_TRY(launch_zero(c->adj.J + kAdjJPart, adj_jpart_slots(np), c->stream));
   HIP_TRY(launch_zero(c->adj.dA, std::max<int64_t>(1, nio * n), c->stream));
   Revolve R;
   R.c = c;
@@ -1745,10 +1859,6 @@ hlb_status adjoint_sweep(hlb_ctx *c, int64_t n, int64_t obj_t0, int64_t obj_t1, 
   R.slot_t.assign(n_snap, 0);
   hlb_status st = R.save(0);
   if (!st) st = R.reverse(t_start, t_start + n, 0, n_snap - 1);
-  if (!st) {
-    hipError_t e = launch_adjoint_finish(c->adj, np, c->stream);
-    if (e != hipSuccess) st = fail(HLB_EDEVICE, "adjoint objective sum: %s", hipGetErrorString(e));
-  }
   // put the caller's state back
   if (!st) {
     hipError_t e = hipMemcpyAsync(c->d.f[cur0], c->adj_slots[0], buf_bytes(c), hipMemcpyDeviceToDevice, c->stream);

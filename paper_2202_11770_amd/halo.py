@@ -11,13 +11,24 @@ differ; every list is ordered by (global site, direction), so sender and
 receiver agree without negotiation.
 
 ``SplitSimulation`` runs one context per part on one GPU, each on its own
-stream, with the transfers on a third stream per part: per step every part
-updates its edge sites and packs them (``hlb_step_edge``), the transfers
-start as soon as the sender's pack is done, the mid-domain update
-(``hlb_step_mid``) runs meanwhile, and each part unpacks before its next
-step.  The transfer is a device copy here; between GPUs it would be an RCCL
-send/recv of the same buffers.  All of the update, pack and unpack runs in
-libhlb; torch provides the buffers, streams and events.
+stream.  Per step every part updates its edge sites (``hlb_step_edge``) and
+then its mid-domain sites (``hlb_step_mid``), which overlap the exchange.
+Two exchanges are built:
+
+* ``exchange="direct"`` (default): the edge step writes each exchanged
+  value straight into the ghost slot of the peer's population buffer that
+  the peer's next step pulls from (``hlb_halo_ghost_slots``,
+  ``hlb_halo_add_peer``): no receive buffer, no transfer, no unpack.  A
+  part's edge step waits only for its peers' previous edge steps (the last
+  readers of the ghost slots it overwrites, and the writers of the ones it
+  reads).  Between GPUs the peer buffer would be mapped over xGMI.
+* ``exchange="copy"``: the edge step packs into a send buffer, a device copy
+  on a transfer stream moves it into the peer's receive buffer, and the
+  peer unpacks it into its ghost slots after its mid-domain update (the
+  shape of an RCCL send/recv of the same buffers).
+
+All of the update, pack and unpack runs in libhlb; torch provides the
+buffers, streams and events.
 """
 from __future__ import annotations
 
@@ -102,12 +113,16 @@ class SplitSimulation:
     """One context per part on one GPU; see the module docstring."""
 
     def __init__(self, geom, tau: float, storage: str = "f64", tables=None, nparts: int = 2, xcd_remap: int = 8,
-                 shared_stream: bool = False):
+                 shared_stream: bool = False, exchange: str = "direct"):
         """shared_stream: all parts' updates on one stream (their kernels run
         back to back) instead of one stream per part (they may overlap); the
-        transfers have their own streams either way."""
+        transfers of the copy exchange have their own streams either way.
+        exchange: "direct" or "copy" (module docstring)."""
         import torch
+        if exchange not in ("direct", "copy"):
+            raise ValueError(f"exchange must be 'direct' or 'copy', not {exchange!r}")
         self.torch = torch
+        self.direct = exchange == "direct"
         self.n = int(geom.types.shape[0])
         self.parts = partition(geom, nparts)
         dt = getattr(torch, _DTYPE[storage])
@@ -129,9 +144,13 @@ class SplitSimulation:
             sd = np.concatenate([P.send[q][1] for q in peers_s]) if peers_s else np.zeros(0, np.int32)
             rs = np.concatenate([P.recv[q][0] for q in peers_r]) if peers_r else np.zeros(0, np.int32)
             rd = np.concatenate([P.recv[q][1] for q in peers_r]) if peers_r else np.zeros(0, np.int32)
-            sb = torch.empty(max(ss.size, 1), dtype=dt, device="cuda")
-            rb = torch.empty(max(rs.size, 1), dtype=dt, device="cuda")
-            hlb.hlb_halo_set(ctx, ss, sd, sb, rs, rd, rb)
+            if self.direct:  # no buffers: the peers are wired below
+                sb = torch.empty(0, dtype=dt, device="cuda")
+                rb = torch.empty(0, dtype=dt, device="cuda")
+            else:
+                sb = torch.empty(max(ss.size, 1), dtype=dt, device="cuda")
+                rb = torch.empty(max(rs.size, 1), dtype=dt, device="cuda")
+                hlb.hlb_halo_set(ctx, ss, sd, sb, rs, rd, rb)
             off, sl = 0, {}
             for q in peers_s:
                 sl[q] = slice(off, off + P.send[q][0].size)
@@ -150,6 +169,18 @@ class SplitSimulation:
             self.send.append(sb)
             self.recv.append(rb)
         self.unpacked = [None] * len(self.parts)
+        # direct exchange: each part writes its send list into the peers'
+        # ghost slots; the peer's receive list names the same (site,
+        # direction) pairs in the same order
+        self.nb = [sorted(set(P.send) | set(P.recv)) for P in self.parts]
+        if self.direct:
+            for r, P in enumerate(self.parts):
+                for q in sorted(P.send):
+                    sites, dirs = P.send[q]
+                    rs, rd = self.parts[q].recv[r]
+                    elem, bufs = hlb.hlb_halo_ghost_slots(self.ctx[q], rs, rd)
+                    hlb.hlb_halo_add_peer(self.ctx[r], sites, dirs, bufs[0], bufs[1], elem)
+        self.edge_done = [None] * len(self.parts)
         self.exchange()
 
     def _transfer(self, packed):
@@ -184,6 +215,14 @@ class SplitSimulation:
         """Fill every ghost from its owner's current state (after creation,
         init or set_state)."""
         torch = self.torch
+        if self.direct:
+            torch.cuda.synchronize()  # every part's state is settled before any peer writes its ghosts
+            for r, ctx in enumerate(self.ctx):
+                hlb.hlb_halo_pack(ctx)
+                e = torch.cuda.Event()
+                e.record(self.s[r])
+                self.edge_done[r] = e
+            return
         packed = []
         for r, ctx in enumerate(self.ctx):
             hlb.hlb_halo_pack(ctx)
@@ -204,6 +243,22 @@ class SplitSimulation:
 
     def step(self, n: int = 1):
         torch = self.torch
+        if self.direct:
+            for _ in range(n):
+                done = []
+                for r, ctx in enumerate(self.ctx):
+                    # the peers' previous edge steps wrote the ghosts this one
+                    # reads and were the last to read the ghosts it writes
+                    for q in self.nb[r]:
+                        self.s[r].wait_event(self.edge_done[q])
+                    hlb.hlb_step_edge(ctx)
+                    e = torch.cuda.Event()
+                    e.record(self.s[r])
+                    done.append(e)
+                for ctx in self.ctx:
+                    hlb.hlb_step_mid(ctx)
+                self.edge_done = done
+            return
         for _ in range(n):
             packed = []
             for r, ctx in enumerate(self.ctx):

@@ -114,6 +114,9 @@ _SIGS = {
     "hlb_create_part": [_i64, _P, _P, _P, _d, _P, _i32, ctypes.POINTER(hlb_options), _P, _PP],
     "hlb_halo_set": [_P, _i64, _P, _P, _P, _i64, _P, _P, _P],
     "hlb_halo_pack": [_P],
+    "hlb_halo_ghost_slots": [_P, _i64, _P, _P, _P, _P],
+    "hlb_halo_add_peer": [_P, _i64, _P, _P, _P, _P, _P],
+    "hlb_halo_clear_peers": [_P],
     "hlb_halo_unpack": [_P],
     "hlb_step_edge": [_P],
     "hlb_step_mid": [_P],
@@ -261,6 +264,29 @@ def hlb_halo_set(ctx, send_site, send_dir, send_buf, recv_site, recv_dir, recv_b
     rd, rdp = _host(recv_dir, np.int32)
     _check(load().hlb_halo_set(ctx, ss.size, ssp, sdp, _devptr(send_buf), rs.size, rsp, rdp, _devptr(recv_buf)),
            "hlb_halo_set")
+
+
+def hlb_halo_ghost_slots(ctx, site, dirs):
+    """Element index of each (ghost site, direction) slot in the partition's
+    population buffers, and the two buffers' device addresses."""
+    sp, spp = _host(site, np.int32)
+    dp, dpp = _host(dirs, np.int32)
+    elem = np.empty(sp.size, dtype=np.int64)
+    bufs = (ctypes.c_void_p * 2)()
+    _check(load().hlb_halo_ghost_slots(ctx, sp.size, spp, dpp, elem.ctypes.data_as(_P), bufs),
+           "hlb_halo_ghost_slots")
+    return elem, (bufs[0], bufs[1])
+
+
+def hlb_halo_add_peer(ctx, site, dirs, peer_buf0, peer_buf1, peer_elem):
+    sp, spp = _host(site, np.int32)
+    dp, dpp = _host(dirs, np.int32)
+    ep, epp = _host(peer_elem, np.int64)
+    _check(load().hlb_halo_add_peer(ctx, sp.size, spp, dpp, _P(peer_buf0), _P(peer_buf1), epp), "hlb_halo_add_peer")
+
+
+def hlb_halo_clear_peers(ctx):
+    _check(load().hlb_halo_clear_peers(ctx), "hlb_halo_clear_peers")
 
 
 def hlb_halo_pack(ctx):

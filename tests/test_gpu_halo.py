@@ -3,8 +3,10 @@ hlb_step_edge / hlb_step_mid, paper_2202_11770_amd/halo.py).
 
 Each site's update reads the same values in the same order whether its
 neighbours are owned or ghost copies, so the split run must reproduce the
-single-domain run bit for bit, in every storage; and, independently of the
-single-domain path, it must match the FP64 oracle site by site.
+single-domain run bit for bit, in every storage and with either exchange
+(direct writes into the peers' ghost slots, or send buffer, copy and
+unpack); and, independently of the single-domain path, it must match the
+FP64 oracle site by site.
 """
 import numpy as np
 import pytest
@@ -25,22 +27,23 @@ def _tree(seed=3, generations=3, target=30000):
     return g, tables
 
 
+@pytest.mark.parametrize("exchange", ["direct", "copy"])
 @pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
 @pytest.mark.parametrize("case", ["tree2", "cylinder2", "tree3"])
-def test_split_matches_single_domain_bitwise(case, storage):
+def test_split_matches_single_domain_bitwise(case, storage, exchange):
     if case == "cylinder2":
         g, tables, tau, steps, k = G.cylinder(), None, 0.8, 500, 2
     elif case == "tree2":
         (g, tables), tau, steps, k = _tree(), 0.6, 300, 2
     else:
         (g, tables), tau, steps, k = _tree(5, 4, 60000), 0.6, 200, 3
-    print(f"case: {case} {g.n} sites, {k} parts, {steps} steps, {storage}", flush=True)
+    print(f"case: {case} {g.n} sites, {k} parts, {steps} steps, {storage}, {exchange} exchange", flush=True)
     sim = hlb.Simulation.create(g, tau, storage=storage, tables=tables)
     sim.step(steps)
     rho, u, wss = sim.macros()
     m, _ = hlb.hlb_mass_balance(sim.ctx)
     sim.close()
-    sp = halo.SplitSimulation(g, tau, storage=storage, tables=tables, nparts=k)
+    sp = halo.SplitSimulation(g, tau, storage=storage, tables=tables, nparts=k, exchange=exchange)
     sp.step(steps)
     sp.synchronize()
     rho2, u2, wss2 = sp.macros()
@@ -81,9 +84,10 @@ def test_split_porous_and_errors():
     with pytest.raises(hlb.HLBError, match="hlb_step_edge must come first"):
         hlb.hlb_step_mid(ctx)
     mid = np.nonzero(P.role == hlb.HLB_PART_MID)[0][:1].astype(np.int32)
+    import torch
+    buf = torch.empty(4, dtype=torch.float64, device="cuda")
     with pytest.raises(hlb.HLBError, match="edge site"):
-        hlb.hlb_halo_set(ctx, mid, np.ones(1, np.int32), sp.send[0], np.zeros(0, np.int32),
-                         np.zeros(0, np.int32), sp.recv[0])
+        hlb.hlb_halo_set(ctx, mid, np.ones(1, np.int32), buf, np.zeros(0, np.int32), np.zeros(0, np.int32), buf)
     sp.close()
 
 
@@ -129,3 +133,27 @@ def test_split_against_oracle(case, storage):
         assert abs(m - P.mass(f)) <= 1e-12 * m
     else:
         check_bars(e, SPLIT_BARS[case][storage], f"split {case} {storage}")
+
+
+def test_direct_exchange_entry_points():
+    """hlb_halo_ghost_slots / hlb_halo_add_peer argument checks, and the
+    element indices of ghost slots lie inside the population buffers."""
+    g, tables = _tree()
+    sp = halo.SplitSimulation(g, 0.6, tables=tables, nparts=2)
+    P0, P1 = sp.parts
+    ctx0, ctx1 = sp.ctx
+    rs, rd = P1.recv[0]
+    elem, bufs = hlb.hlb_halo_ghost_slots(ctx1, rs, rd)
+    info = hlb.hlb_info(ctx1)
+    assert elem.min() >= 0 and elem.max() < 19 * info["n_padded"]
+    assert bufs[0] and bufs[1] and bufs[0] != bufs[1]
+    owned = np.nonzero(P1.role != hlb.HLB_PART_GHOST)[0][:1].astype(np.int32)
+    with pytest.raises(hlb.HLBError, match="ghost site"):
+        hlb.hlb_halo_ghost_slots(ctx1, owned, np.ones(1, np.int32))
+    mid = np.nonzero(P0.role == hlb.HLB_PART_MID)[0][:1].astype(np.int32)
+    with pytest.raises(hlb.HLBError, match="edge site"):
+        hlb.hlb_halo_add_peer(ctx0, mid, np.ones(1, np.int32), bufs[0], bufs[1], elem[:1])
+    sites, dirs = P0.send[1]
+    with pytest.raises(hlb.HLBError, match="negative"):
+        hlb.hlb_halo_add_peer(ctx0, sites[:1], dirs[:1], bufs[0], bufs[1], -np.ones(1, np.int64))
+    sp.close()
