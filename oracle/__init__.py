@@ -40,7 +40,7 @@ def build(verbose: bool = False) -> str:
 class _Iolet(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("role", ctypes.c_int32), ("centre", ctypes.c_double * 3),
                 ("normal", ctypes.c_double * 3), ("radius", ctypes.c_double), ("vdir", ctypes.c_double * 3),
-                ("table", ctypes.c_void_p), ("table_len", ctypes.c_int64)]
+                ("table", ctypes.c_void_p), ("table_len", ctypes.c_int64), ("rho_local", ctypes.c_int32)]
 
 
 def _load():
@@ -96,7 +96,10 @@ def _c64(a, dtype=np.float64):
 class Problem:
     """A geometry plus the physics parameters the oracle needs, marshalled once."""
 
-    def __init__(self, geom, tau: float, rho0: float = 1.0, tables=None, phi=None):
+    def __init__(self, geom, tau: float, rho0: float = 1.0, tables=None, phi=None, ladd_rho_local: bool = False):
+        """ladd_rho_local: the Ladd rule takes each site's own density at t
+        instead of rho0 (forward update only)."""
+        self.ladd_rho_local = bool(ladd_rho_local)
         self.n = int(geom.coords.shape[0])
         self.coords = np.ascontiguousarray(geom.coords, dtype=np.int32)
         self.nbr = np.ascontiguousarray(geom.nbr, dtype=np.int32)
@@ -120,6 +123,7 @@ class Problem:
             ios[k].vdir[:] = [float(v) for v in vd]
             ios[k].table = tab.ctypes.data_as(ctypes.c_void_p)
             ios[k].table_len = tab.size
+            ios[k].rho_local = 1 if (self.ladd_rho_local and int(io.kind) == 0) else 0
         self.io = ios
         self.n_io = len(geom.iolets)
 
@@ -173,6 +177,8 @@ class Problem:
         or ghost density) and the per-site porosity [n], and with
         state_grad also the derivative with respect to f0 [n][19].  Keeps all
         nsteps+1 states in memory."""
+        if self.ladd_rho_local:
+            raise ValueError("the reference adjoint takes the Ladd rule with rho0")
         f0 = np.ascontiguousarray(f0, dtype=np.float64)
         J = np.zeros(1)
         dA = np.zeros((max(self.n_io, 1), nsteps))
@@ -194,6 +200,8 @@ class Problem:
         """Tangent-linear model (oracle_tangent.c): the derivative of the
         objective of adjoint() in the direction (df0 [n][19], dtab
         [n_io][nsteps], dphi [n]); each part may be None (zero)."""
+        if self.ladd_rho_local:
+            raise ValueError("the tangent-linear model takes the Ladd rule with rho0")
         f0 = np.ascontiguousarray(f0, dtype=np.float64)
         dJ = np.zeros(1)
         w = None if weights is None else np.ascontiguousarray(weights, dtype=np.float64)

@@ -124,17 +124,19 @@ static void kadd(kahan *k, double v) {
 /* The population an iolet returns to site x (coordinates xc) in direction
  * opp(i) when the post-collision f'_i(x) = fp[i] leaves through it during the
  * update t -> t+1; u is the site's velocity at t.
- *   Ladd (Sec. 2.3.2): bounce-back plus -2 w_i rho c_i.U / cs^2, rho = rho0,
- *     U taken at the link midpoint x + c_i/2;
+ *   Ladd (Sec. 2.3.2): bounce-back plus -2 w_i rho c_i.U / cs^2, rho = rho0
+ *     (or, with rho_local, the site's density rho_x at t), U taken at the
+ *     link midpoint x + c_i/2;
  *   ghost density (Sec. 2.3.2): the equilibrium at the iolet density
  *     rho_k(t) and the site velocity projected on the iolet normal. */
-static double iolet_fill(const orc_iolet *K, const int32_t *xc, int i, int64_t t, double rho0, const double *fp,
-                         const double *u) {
+static double iolet_fill(const orc_iolet *K, const int32_t *xc, int i, int64_t t, double rho0, double rho_x,
+                         const double *fp, const double *u) {
   if (K->kind == 0) {
     const double m[3] = {xc[0] + 0.5 * C[i][0], xc[1] + 0.5 * C[i][1], xc[2] + 0.5 * C[i][2]};
     double U[3];
     iolet_velocity(K, m, t, U);
-    return fp[i] - 2.0 * W[i] * rho0 * cdot(i, U) / CS2;
+    const double rw = K->rho_local ? rho_x : rho0;
+    return fp[i] - 2.0 * W[i] * rw * cdot(i, U) / CS2;
   }
   const double *nk = K->normal;
   const double un = u[0] * nk[0] + u[1] * nk[1] + u[2] * nk[2];
@@ -162,7 +164,7 @@ int orc_iolet_flux(int64_t n, const int32_t *coords, const int32_t *nbr, double 
       if (y >= ORC_WALL) continue;
       const int32_t k = -(y + 2);
       if (k < 0 || k >= n_io) { bad = 1; continue; }
-      Q[k] += fp[i] - iolet_fill(io + k, coords + 3 * x, i, t, rho0, fp, u);
+      Q[k] += fp[i] - iolet_fill(io + k, coords + 3 * x, i, t, rho0, rho, fp, u);
     }
   }
   return bad ? -1 : 0;
@@ -212,7 +214,7 @@ int orc_step(int64_t n, const int32_t *coords, const int32_t *nbr, double tau, d
           const int32_t k = -(y + 2);
           if (k < 0 || k >= n_io) { bad = 1; continue; }
           slot = ORC_Q * x + OPP[i];
-          val = iolet_fill(io + k, coords + 3 * x, i, t, rho0, fp, u);
+          val = iolet_fill(io + k, coords + 3 * x, i, t, rho0, rho, fp, u);
           kadd(&acc, val - fp[i]);
         }
         F[slot] = val;

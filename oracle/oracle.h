@@ -50,6 +50,10 @@ typedef struct {
   double vdir[3];    /* direction of the imposed velocity; all zero: normal */
   const double *table; /* per-step amplitude A_k(s) or ghost density rho_k(s) */
   int64_t table_len;   /* value at step s is table[s mod table_len] */
+  int32_t rho_local;   /* velocity kind: 1 = the Ladd term takes the site's own
+                          density at t, 0 = the reference density rho0 (the
+                          forward update only; the adjoint and tangent codes
+                          take rho0) */
 } orc_iolet;
 
 /* Lattice constants as the oracle uses them (for the tests). */

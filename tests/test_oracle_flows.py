@@ -138,6 +138,30 @@ def test_couette_ladd(orc, tau):
     assert np.abs(rho - 1.0).max() <= 1e-10
 
 
+@pytest.mark.parametrize("local", [False, True], ids=["rho0", "rho_local"])
+def test_couette_ladd_density(orc, local):
+    """The Ladd lid in a fluid whose density differs from rho0 (uniform
+    rho = 1.2, rho0 = 1): its momentum term carries rho0 (Sec. 2.3.2 read as
+    a fixed reference density), so the lid acts as one moving at
+    U rho0 / rho, and the steady profile is the linear one scaled by
+    rho0 / rho; with the site's own density in the term (the local-density
+    reading) the lid moves at U and the profile is exactly U (z + 1/2) / H.
+    Either way the closed form holds to the convergence of the run."""
+    H, U, tau, rho = 8, 0.01, 0.8, 1.2
+    g = G.couette_column(H, U)
+    P = orc.Problem(g, tau, rho0=1.0, ladd_rho_local=local)
+    f = P.init(np.full(g.n, rho), None)
+    P.run(f, 0, 40000)
+    r, u, _ = P.macros(f)
+    z = g.coords[:, 2].astype(float)
+    exact = U * (z + 0.5) / H * (1.0 if local else 1.0 / rho)
+    assert np.abs(u[:, 0] - exact).max() <= 1e-10 * U
+    assert np.abs(r - rho).max() <= 1e-10
+    if local:
+        with pytest.raises(ValueError):
+            P.adjoint(P.init(), 0, 2, 0, 2)
+
+
 def _duct_series(y, z, a, b, G_, eta, nterms=201):
     """Steady velocity in the rectangular duct |y| <= a, |z| <= b under a
     pressure gradient -G_ (textbook Fourier series)."""

@@ -25,6 +25,7 @@ ADJ = "tests/test_oracle_adjoint.py"
 TAN = "tests/test_oracle_tangent.py"
 REST = FLOWS + "::test_rest_state_all_boundary_kinds"
 COUETTE = FLOWS + "::test_couette_ladd"
+COUETTE_RHO = FLOWS + "::test_couette_ladd_density"
 PIPE = FLOWS + "::test_cylinder_poiseuille"
 DUCT = FLOWS + "::test_duct_pressure_poiseuille"
 POROUS = FLOWS + "::test_porous_box_relaxes_to_reservoir"
@@ -47,10 +48,15 @@ MUTANTS = [
     ("bounce_back_slot", "oracle.c", "slot = ORC_Q * x + OPP[i];\n          val = (1.0 - ph)",
      "slot = ORC_Q * x + i;\n          val = (1.0 - ph)", [REST]),
     # Ladd term with the wrong sign, and with the wrong factor
-    ("ladd_sign", "oracle.c", "return fp[i] - 2.0 * W[i] * rho0 * cdot(i, U) / CS2;",
-     "return fp[i] + 2.0 * W[i] * rho0 * cdot(i, U) / CS2;", [COUETTE]),
-    ("ladd_factor", "oracle.c", "return fp[i] - 2.0 * W[i] * rho0 * cdot(i, U) / CS2;",
-     "return fp[i] - 1.0 * W[i] * rho0 * cdot(i, U) / CS2;", [COUETTE]),
+    ("ladd_sign", "oracle.c", "return fp[i] - 2.0 * W[i] * rw * cdot(i, U) / CS2;",
+     "return fp[i] + 2.0 * W[i] * rw * cdot(i, U) / CS2;", [COUETTE]),
+    ("ladd_factor", "oracle.c", "return fp[i] - 2.0 * W[i] * rw * cdot(i, U) / CS2;",
+     "return fp[i] - 1.0 * W[i] * rw * cdot(i, U) / CS2;", [COUETTE]),
+    # Ladd density: the local-density option ignored, or taken in both modes
+    ("ladd_density_ignored", "oracle.c", "const double rw = K->rho_local ? rho_x : rho0;",
+     "const double rw = rho0;", [COUETTE_RHO]),
+    ("ladd_density_always_local", "oracle.c", "const double rw = K->rho_local ? rho_x : rho0;",
+     "const double rw = rho_x;", [COUETTE_RHO]),
     # ghost-density rule returns the equilibrium of the outgoing direction
     ("pressure_direction", "oracle.c", "return fg[OPP[i]];", "return fg[i];", [PIPE, DUCT]),
     # ghost velocity reversed
