@@ -98,7 +98,8 @@ enum { HLB_ROLE_INLET = 0, HLB_ROLE_OUTLET = 1 };
 
 /* One inlet or outlet ("iolet", Sec. 2.3.2).
  * Velocity kind (Ladd): a population leaving site x along c_i through the
- * iolet comes back as f'_i - 6 w_i rho0 (c_i . U), U = A_k(s) W(m) v_k, with
+ * iolet comes back as f'_i - 6 w_i rho0 (c_i . U) (rho0 replaced by the
+ * site's density at s with hlb_options.ladd_rho_local), U = A_k(s) W(m) v_k, with
  * m = x + c_i/2 the link midpoint, W(m) = max(0, 1 - d^2/R^2) where d is the
  * distance of m from the iolet axis (centre, normal) (W = 1 if radius <= 0),
  * and v_k = vdir (the normal if vdir is zero).
@@ -143,6 +144,10 @@ typedef struct {
   int32_t order_block; /* log2 of the band / column width of
                           HLB_ORDER_BANDS and HLB_ORDER_COLUMNS, 1..16
                           (default 6); ignored by the other orders */
+  int32_t ladd_rho_local; /* density in the Ladd rule (Sec. 2.3.2):
+                          0 (default) the reference density rho0;
+                          1 the site's own density at the time of the
+                          update (not with adjoint = 1) */
 } hlb_options;
 
 /* Order of the fused update (Sec. 3.2 implements push and names pull as

@@ -242,6 +242,7 @@ struct GatherArgs {
   const int64_t *t_base;  // non-null inside a replayed graph: the time is *t_base + t
   const double *phi;   // porosity or null
   double rho0;
+  int ladd_local;      // 1: the Ladd term takes the site's own density at t (else rho0)
 };
 
 // Time of the update an iolet rule belongs to (see GatherArgs::t_base).
@@ -390,19 +391,21 @@ __device__ inline C gather(const T *__restrict__ A, int64_t p, int64_t blk, cons
       g[i] = v;
     }
   } else {
-    // velocity at time t: moments of the site's own post-collision state
-    // (the collision conserves rho and rho u)
-    C ux, uy, uz;
+    // density and velocity at time t: moments of the site's own
+    // post-collision state (the collision conserves rho and rho u)
+    C ux, uy, uz, rho_x;
     {
       C own[Q];
 #pragma unroll
       for (int i = 0; i < Q; ++i) own[i] = ld(at<NARROW>(A, (int32_t)p, i));
-      C dr, rho, jx, jy, jz;
-      moments<SH>(own, C(a.rho0), dr, rho, jx, jy, jz);
-      ux = jx / rho;
-      uy = jy / rho;
-      uz = jz / rho;
+      C dr, jx, jy, jz;
+      moments<SH>(own, C(a.rho0), dr, rho_x, jx, jy, jz);
+      ux = jx / rho_x;
+      uy = jy / rho_x;
+      uz = jz / rho_x;
     }
+    // the Ladd coefficients hold rho0; the local-density rule rescales them
+    const double ladd_scale = a.ladd_local ? double(rho_x) / a.rho0 : 1.0;
     // The reflected values are read again below (cache hits) instead of
     // being kept live with the 19 gathered ones: the empty asm hides that
     // q == p, so the compiler cannot merge those reads with the ones above
@@ -428,7 +431,7 @@ __device__ inline C gather(const T *__restrict__ A, int64_t p, int64_t blk, cons
         const IoletDev K = a.io[k];
         const double val = K.wk ? a.wk_rho[2 * k + (t & 1)] : a.tables[K.tab_off + t % K.tab_len];
         if (K.kind == HLB_IOLET_VELOCITY) {
-          v = back + C(a.corr[(int64_t)(i - 1) * a.nio + (p - a.io_begin)] * val);
+          v = back + C(a.corr[(int64_t)(i - 1) * a.nio + (p - a.io_begin)] * val * ladd_scale);
         } else {
           const C un = ux * C(K.n[0]) + uy * C(K.n[1]) + uz * C(K.n[2]);
           const C gx = un * C(K.n[0]), gy = un * C(K.n[1]), gz = un * C(K.n[2]);
@@ -499,12 +502,13 @@ __device__ inline void gather_bulk2(const T *__restrict__ A, int64_t p, int64_t 
 // x + c_j, or, when that link leaves the fluid, the site's own slot opp(j)
 // with the boundary rule's value (the rules of gather(), seen from the
 // leaving side).  The site's link to x + c_j is the pull entry of direction
-// opp(j), so the pull tables serve both orders.  (ux, uy, uz): the site's
-// velocity at t, for the pressure rule.  Returns the mass the boundary rules
+// opp(j), so the pull tables serve both orders.  (ux, uy, uz), rho_x: the
+// site's velocity and density at t, for the pressure rule and the
+// local-density Ladd rule.  Returns the mass the boundary rules
 // added.
 template <bool IOLET, bool POROUS, bool SH, bool NARROW, typename T, typename C>
 __device__ inline C scatter(T *__restrict__ B, int64_t p, int64_t blk, const GatherArgs &a, const C (&fp)[Q], C ux,
-                            C uy, C uz, WkFlux *wkf = nullptr) {
+                            C uy, C uz, C rho_x, WkFlux *wkf = nullptr) {
   const int64_t np = a.np;
   const int32_t p32 = (int32_t)p;
   C flux = 0;
@@ -528,6 +532,7 @@ __device__ inline C scatter(T *__restrict__ B, int64_t p, int64_t blk, const Gat
     }
   } else {
     const int64_t t = step_time(a);
+    const double ladd_scale = a.ladd_local ? double(rho_x) / a.rho0 : 1.0;
 #pragma unroll
     for (int j = 1; j < Q; ++j) {
       const int i = opp(j);  // the direction the boundary fills at p
@@ -546,7 +551,7 @@ __device__ inline C scatter(T *__restrict__ B, int64_t p, int64_t blk, const Gat
         const IoletDev K = a.io[k];
         const double val = K.wk ? a.wk_rho[2 * k + (t & 1)] : a.tables[K.tab_off + t % K.tab_len];
         if (K.kind == HLB_IOLET_VELOCITY) {
-          v = back + C(a.corr[(int64_t)(i - 1) * a.nio + (p - a.io_begin)] * val);
+          v = back + C(a.corr[(int64_t)(i - 1) * a.nio + (p - a.io_begin)] * val * ladd_scale);
         } else {
           const C un = ux * C(K.n[0]) + uy * C(K.n[1]) + uz * C(K.n[2]);
           const C gx = un * C(K.n[0]), gy = un * C(K.n[1]), gz = un * C(K.n[2]);
@@ -580,6 +585,7 @@ inline GatherArgs make_args(const LaunchCfg &cfg, const Layout &L, const DevPtrs
   a.t_base = d.t_base;
   a.phi = cfg.porous ? d.phi : nullptr;
   a.rho0 = cfg.rho0;
+  a.ladd_local = cfg.ladd_local ? 1 : 0;
   return a;
 }
 

@@ -99,6 +99,7 @@ struct LaunchCfg {
   bool porous = false;
   int scheme = HLB_SCHEME_PULL;
   int sites_per_thread = 1;  // bulk+wall sites per thread in the full pull step (1 or 2)
+  bool ladd_local = false;   // Ladd rule with the site's own density (hlb_options.ladd_rho_local)
 };
 
 // Bulk+wall sites per thread of the full pull step for a storage type when
@@ -141,6 +142,8 @@ struct AdjBuffers {
   int64_t n_blist_wall = 0;   // leading entries below the iolet groups (wall links only)
   int32_t objective = HLB_OBJ_WSS;
   double *w = nullptr;        // [n_iolets] iolet-flux weights (device)
+  int32_t *bidx = nullptr;    // [np] index in blist per position, -1 if none
+  double *wrec = nullptr;     // [n_blist][6] WSS-term records of the step in flight
 };
 // Adjoint of the update (t-1 -> t): buffer `src` holds s_{t-1}; b.mu holds
 // mu_t on entry and mu_{t-1} on return; accumulates J (if in_window), the
@@ -149,6 +152,8 @@ struct AdjBuffers {
 hipError_t launch_adjoint_step(const LaunchCfg &cfg, const Layout &L, const DevPtrs &d, int src, int64_t t,
                                const AdjBuffers &b, int in_window, int64_t n_steps, int64_t step,
                                hipStream_t s);
+// b.bidx of the list b.blist (np positions, n list entries).
+hipError_t launch_adjoint_index(int32_t *bidx, int64_t np, const int32_t *blist, int64_t n, hipStream_t s);
 // p[0..n) := 0 (a kernel, so that no memset node lands in a captured graph).
 hipError_t launch_zero(double *p, int64_t n, hipStream_t s);
 // After the update t -> t+1: Windkessel outlets take their outflow, advance

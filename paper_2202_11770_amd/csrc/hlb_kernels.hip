@@ -146,7 +146,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kStepWav
       C dr, rho, jx, jy, jz;
       moments<SH>(f, C(a.rho0), dr, rho, jx, jy, jz);
       collide<SH>(f, omega, C(a.rho0));
-      flux = scatter<true, POROUS, SH, NARROW>(B, p, 0, a, f, jx / rho, jy / rho, jz / rho, &wkf);
+      flux = scatter<true, POROUS, SH, NARROW>(B, p, 0, a, f, jx / rho, jy / rho, jz / rho, rho, &wkf);
     }
     const double s = wave_sum(double(flux));
     if ((threadIdx.x & 63) == 0 && s != 0.0) atomicAdd(acc, s);
@@ -159,7 +159,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kStepWav
 #pragma unroll
       for (int i = 0; i < Q; ++i) f[i] = ld(at<NARROW>(A, (int32_t)p, i));
       collide<SH>(f, omega, C(a.rho0));
-      flux = scatter<false, POROUS, SH, NARROW>(B, p, blk, a, f, C(0), C(0), C(0));
+      flux = scatter<false, POROUS, SH, NARROW>(B, p, blk, a, f, C(0), C(0), C(0), C(0));
     }
     if constexpr (POROUS) {
       const double s = wave_sum(double(flux));

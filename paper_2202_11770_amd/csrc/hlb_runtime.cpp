@@ -145,7 +145,8 @@ bool same_launch(const DevPtrs &a, const DevPtrs &b) {
 }
 bool same_launch(const LaunchCfg &a, const LaunchCfg &b) {
   return a.storage == b.storage && a.tau == b.tau && a.rho0 == b.rho0 && a.xcd_chunk == b.xcd_chunk &&
-         a.porous == b.porous && a.scheme == b.scheme && a.sites_per_thread == b.sites_per_thread;
+         a.porous == b.porous && a.scheme == b.scheme && a.sites_per_thread == b.sites_per_thread &&
+         a.ladd_local == b.ladd_local;
 }
 
 }  // namespace
@@ -435,6 +436,7 @@ hlb_status hlb_default_options(hlb_options *opt) {
   opt->sites_per_thread = 0;
   opt->graph_steps = 0;
   opt->order_block = 6;
+  opt->ladd_rho_local = 0;
   return HLB_OK;
 }
 
@@ -457,6 +459,10 @@ static hlb_status create_impl(int64_t n, const int32_t *coords, const uint8_t *t
   if (opt.order < HLB_ORDER_INPUT || opt.order > HLB_ORDER_COLUMNS) return fail(HLB_EINVAL, "bad order %d", opt.order);
   if (opt.order_block < 1 || opt.order_block > 16)
     return fail(HLB_EINVAL, "order_block must be in 1..16 (got %d)", opt.order_block);
+  if (opt.ladd_rho_local != 0 && opt.ladd_rho_local != 1)
+    return fail(HLB_EINVAL, "ladd_rho_local must be 0 or 1 (got %d)", opt.ladd_rho_local);
+  if (opt.ladd_rho_local && opt.adjoint)
+    return fail(HLB_EINVAL, "the adjoint takes the Ladd rule with rho0 (ladd_rho_local must be 0)");
   if (!(opt.rho0 > 0.0) || !std::isfinite(opt.rho0)) return fail(HLB_EINVAL, "rho0 must be finite and > 0");
   if ((opt.adjoint != 0 && opt.adjoint != 1) || opt.max_device_bytes < 0 || opt.xcd_remap < 0 ||
       opt.xcd_remap > (1 << 20))
@@ -555,6 +561,7 @@ static hlb_status create_impl(int64_t n, const int32_t *coords, const uint8_t *t
   c->cfg.porous = false;
   c->cfg.scheme = opt.scheme;
   c->cfg.sites_per_thread = opt.sites_per_thread > 0 ? opt.sites_per_thread : default_sites_per_thread(opt.storage);
+  c->cfg.ladd_local = opt.ladd_rho_local != 0;
   c->graph_steps = opt.graph_steps;
   c->order = opt.order;
   c->max_bytes = opt.max_device_bytes;
@@ -1807,7 +1814,7 @@ hlb_status adjoint_sweep(hlb_ctx *c, int64_t n, int64_t obj_t0, int64_t obj_t1, 
                          int64_t *forward_steps) {
   if (n < 1 || n_snap < 1 || n_snap > 4096) return fail(HLB_EINVAL, "need n >= 1, 1 <= n_snap <= 4096");
   if (c->n_wk > 0) return fail(HLB_ESTATE, "the adjoint does not cover Windkessel outlets");
-  if (c->cfg.storage != HLB_F64 || !c->adj_on || c->cfg.scheme != HLB_SCHEME_PULL)
+  if (c->cfg.storage != HLB_F64 || !c->adj_on || c->cfg.scheme != HLB_SCHEME_PULL || c->cfg.ladd_local)
     return fail(HLB_ESTATE, "the adjoint needs FP64 storage and opt.adjoint = 1 at creation");
   if (hlb_status st = bind(c)) return st;
   const int64_t np = c->L.np, nio = (int64_t)c->iolets.size();

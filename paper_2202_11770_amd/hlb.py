@@ -49,7 +49,7 @@ class hlb_options(ctypes.Structure):
     _fields_ = [("storage", ctypes.c_int32), ("order", ctypes.c_int32), ("xcd_remap", ctypes.c_int32),
                 ("adjoint", ctypes.c_int32), ("rho0", ctypes.c_double), ("max_device_bytes", ctypes.c_int64),
                 ("scheme", ctypes.c_int32), ("sites_per_thread", ctypes.c_int32),
-                ("graph_steps", ctypes.c_int32), ("order_block", ctypes.c_int32)]
+                ("graph_steps", ctypes.c_int32), ("order_block", ctypes.c_int32), ("ladd_rho_local", ctypes.c_int32)]
 
 
 class hlb_windkessel(ctypes.Structure):
@@ -527,13 +527,15 @@ class Simulation:
     @classmethod
     def create(cls, geom, tau: float, storage: str = "f64", order: str | None = None, xcd_remap: int = 8,
                rho0: float = 1.0, max_device_bytes: int = 0, tables=None, adjoint: bool = False,
-               scheme: str = "pull", sites_per_thread: int = 0, graph_steps: int = 0, order_block: int = 0):
+               scheme: str = "pull", sites_per_thread: int = 0, graph_steps: int = 0, order_block: int = 0,
+               ladd_rho_local: bool = False):
         """order: the site order (None: the library's default); order_block:
         log2 of the band / column width of the "bands" and "columns" orders
         (0: the library's default)."""
         opt = hlb_default_options()
         if order_block:
             opt.order_block = int(order_block)
+        opt.ladd_rho_local = 1 if ladd_rho_local else 0
         opt.scheme = SCHEME[scheme]
         opt.sites_per_thread = int(sites_per_thread)
         opt.graph_steps = int(graph_steps)

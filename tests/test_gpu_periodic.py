@@ -134,3 +134,64 @@ def test_duct_pressure_iolets():
     say("duct f64:", fmt(e))
     assert e["e_rho"] <= 1e-12 and e["e_u"] <= 1e-12 and e["e_wss"] <= 1e-10
     assert abs(m - m_ref) <= 1e-12 * m
+
+
+@pytest.mark.parametrize("local", [False, True], ids=["rho0", "rho_local"])
+@pytest.mark.parametrize("scheme", ["pull", "push"])
+def test_couette_ladd_density(local, scheme):
+    """Couette column filled at rho = 1.2 with rho0 = 1: with the site's own
+    density in the Ladd rule (hlb_options.ladd_rho_local) the lid moves at
+    U, with rho0 at U rho0 / rho (the oracle's closed-form pin); the GPU
+    matches the oracle site by site in both readings and both orders."""
+    H, U, tau, rho = 8, 0.01, 0.8, 1.2
+    g = G.couette_column(H, U)
+    say(f"case: couette column at rho {rho}, ladd_rho_local {local}, {scheme}, 40000 steps, f64")
+    P = oracle.Problem(g, tau, ladd_rho_local=local)
+    f = P.init(np.full(g.n, rho), None)
+    P.run(f, 0, 40000)
+    ref = P.macros(f)
+    sim = hlb.Simulation.create(g, tau, scheme=scheme, ladd_rho_local=local)
+    hlb.hlb_init_equilibrium(sim.ctx, np.full(g.n, rho), None, 0)
+    sim.step(40000)
+    got = sim.macros()
+    sim.close()
+    e = errors(*got, *ref)
+    say(f"couette rho {rho} local={local} {scheme}:", fmt(e))
+    assert e["e_rho"] <= 1e-12 and e["e_u"] <= 1e-12 and e["e_wss"] <= 1e-10
+    z = g.coords[:, 2].astype(float)
+    exact = U * (z + 0.5) / H * (1.0 if local else 1.0 / rho)
+    assert np.abs(got[1][:, 0] - exact).max() <= 1e-10 * U
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_tree_ladd_density_random_start(storage):
+    """A 30k-site tree from a random start (density 1 +- 0.01 varies from
+    site to site at the Ladd inlet) with the local-density Ladd rule, 200
+    steps, against the oracle with the same reading."""
+    g = G.tree(seed=3, generations=3, target_sites=30000)
+    s = np.arange(200)
+    tables = [0.02 * 0.5 * (1 - np.cos(2 * np.pi * s / 200)) if io.kind == G.VELOCITY else np.array([1.0])
+              for io in g.iolets]
+    init = random_field(g.n, 41)
+    say(f"case: tree {g.n} sites, ladd_rho_local, random start, 200 steps, {storage}")
+    P = oracle.Problem(g, 0.6, tables=tables, ladd_rho_local=True)
+    f = P.init(*init)
+    P.run(f, 0, 200)
+    ref = P.macros(f)
+    P0 = oracle.Problem(g, 0.6, tables=tables)
+    f0 = P0.init(*init)
+    P0.run(f0, 0, 200)
+    sim = hlb.Simulation.create(g, 0.6, storage=storage, tables=tables, ladd_rho_local=True)
+    hlb.hlb_init_equilibrium(sim.ctx, init[0], init[1], 0)
+    sim.step(200)
+    got = sim.macros()
+    sim.close()
+    e = errors(*got, *ref)
+    say(f"tree ladd_rho_local {storage}:", fmt(e), "| rho0 reading vs local:",
+        f"{np.abs(P0.macros(f0)[1] - ref[1]).max():.2e}")
+    # the two readings differ well above the bars (the option is exercised)
+    assert np.abs(P0.macros(f0)[1] - ref[1]).max() > 1e-8
+    if storage == "f64":
+        assert e["e_rho"] <= 1e-12 and e["e_u"] <= 1e-12 and e["e_wss"] <= 1e-10
+    else:
+        check_bars(e, dict(e_rho=5e-7, e_u=2e-5, e_wss=2e-5), "tree ladd_rho_local f32")
