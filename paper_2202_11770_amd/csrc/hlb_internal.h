@@ -130,30 +130,6 @@ hipError_t launch_macros(const LaunchCfg &cfg, const Layout &L, const DevPtrs &d
 // buffer `pre` := f - w rho0, buffer 1-pre := its collision.
 hipError_t launch_set_state(const LaunchCfg &cfg, const Layout &L, const DevPtrs &d, int pre,
                             const double *staging, hipStream_t s);
-// Device buffers of the adjoint sweep (FP64 storage only).
-struct AdjBuffers {
-  double *mu = nullptr;       // adjoint of the post-collision state (tiled, as the state)
-  double *nu = nullptr;       // adjoint of the pre-collision state (tiled, as the state)
-  double *J = nullptr;        // objective accumulator
-  double *dA = nullptr;       // [n_iolets][n_steps]
-  double *dphi = nullptr;     // [np] porosity derivative per position
-  int32_t *blist = nullptr;   // positions of the sites with wall or iolet links, ascending
-  int64_t n_blist = 0;
-  int64_t n_blist_wall = 0;   // leading entries below the iolet groups (wall links only)
-  int32_t objective = HLB_OBJ_WSS;
-  double *w = nullptr;        // [n_iolets] iolet-flux weights (device)
-  int32_t *bidx = nullptr;    // [np] index in blist per position, -1 if none
-  double *wrec = nullptr;     // [n_blist][6] WSS-term records of the step in flight
-};
-// Adjoint of the update (t-1 -> t): buffer `src` holds s_{t-1}; b.mu holds
-// mu_t on entry and mu_{t-1} on return; accumulates J (if in_window), the
-// iolet table-value derivatives into column `step` of dA and the porosity
-// derivatives.
-hipError_t launch_adjoint_step(const LaunchCfg &cfg, const Layout &L, const DevPtrs &d, int src, int64_t t,
-                               const AdjBuffers &b, int in_window, int64_t n_steps, int64_t step,
-                               hipStream_t s);
-// b.bidx of the list b.blist (np positions, n list entries).
-hipError_t launch_adjoint_index(int32_t *bidx, int64_t np, const int32_t *blist, int64_t n, hipStream_t s);
 // p[0..n) := 0 (a kernel, so that no memset node lands in a captured graph).
 hipError_t launch_zero(double *p, int64_t n, hipStream_t s);
 // After the update t -> t+1: Windkessel outlets take their outflow, advance

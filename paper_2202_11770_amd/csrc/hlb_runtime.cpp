@@ -18,6 +18,7 @@
 #include <vector>
 
 #include "hlb.h"
+#include "hlb_adjoint.h"
 #include "hlb_aux.h"
 #include "hlb_halo.h"
 #include "hlb_internal.h"
@@ -1827,7 +1828,7 @@ hlb_status adjoint_sweep(hlb_ctx *c, int64_t n, int64_t obj_t0, int64_t obj_t1, 
     if (hlb_status st = dev_alloc(c, &p, (size_t)np * sizeof(double))) return st;
     c->adj.dphi = static_cast<double *>(p);
     // [0] the objective; [1, 5) the caller's flux accumulators while the sweep runs
-    if (hlb_status st = dev_alloc(c, &p, 8 * sizeof(double))) return st;
+    if (hlb_status st = dev_alloc(c, &p, kAdjJLen * sizeof(double))) return st;
     c->adj.J = static_cast<double *>(p);
   }
   if (c->adj_dA_len < std::max<int64_t>(1, nio * n)) {
@@ -1854,7 +1855,7 @@ hlb_status adjoint_sweep(hlb_ctx *c, int64_t n, int64_t obj_t0, int64_t obj_t1, 
   HIP_TRY(hipMemcpyAsync(c->adj_slots[n_snap], c->d.f[1 - cur0], buf_bytes(c), hipMemcpyDeviceToDevice, c->stream));
   HIP_TRY(launch_zero(c->adj.mu, (int64_t)Q * np, c->stream));
   HIP_TRY(launch_zero(c->adj.dphi, np, c->stream));
-  HIP_TRY(launch_zero(c->adj.J, 1, c->stream));
+  HIP_TRY(launch_zero(c->adj.J + 8, kAdjJSlots, c->stream));
   HIP_TRY(launch_zero(c->adj.dA, std::max<int64_t>(1, nio * n), c->stream));
   Revolve R;
   R.c = c;
@@ -1866,6 +1867,10 @@ hlb_status adjoint_sweep(hlb_ctx *c, int64_t n, int64_t obj_t0, int64_t obj_t1, 
   R.slot_t.assign(n_snap, 0);
   hlb_status st = R.save(0);
   if (!st) st = R.reverse(t_start, t_start + n, 0, n_snap - 1);
+  if (!st) {
+    hipError_t e = launch_adjoint_objective(c->adj.J, c->stream);
+    if (e != hipSuccess) st = fail(HLB_EDEVICE, "objective sum: %s", hipGetErrorString(e));
+  }
   // put the caller's state back
   if (!st) {
     hipError_t e = hipMemcpyAsync(c->d.f[cur0], c->adj_slots[0], buf_bytes(c), hipMemcpyDeviceToDevice, c->stream);
