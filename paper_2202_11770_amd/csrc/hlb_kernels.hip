@@ -41,12 +41,15 @@ using namespace dev;
 // the bulk path does not), and whether population addresses use 32-bit byte
 // offsets when a buffer allows it (see at()).  FP64: the natural 4 waves and
 // 32-bit offsets; FP32: the natural 5 waves and 64-bit addresses (32-bit
-// offsets measured 3% slower); FP16: 8 waves and 32-bit offsets.
+// offsets measured 3% slower); FP16: 8 waves and 32-bit offsets.  FP64 with
+// 64-bit addresses (buffers above 4 GiB, hence the 2e8-site tree): 6 waves,
+// measured 1.4% faster there than 4 (and than 5).
 // SPT = 2 (two bulk+wall sites per thread, see below) needs about twice the
 // registers of the bulk path: 4 waves.
-template <typename T, int SPT = 1>
+template <typename T, int SPT = 1, bool NARROW = true>
 constexpr int kStepWaves =
-    SPT == 2 ? 4 : (std::is_same<T, double>::value ? 4 : (std::is_same<T, float>::value ? 5 : 8));
+    SPT == 2 ? 4
+             : (std::is_same<T, double>::value ? (NARROW ? 4 : 6) : (std::is_same<T, float>::value ? 5 : 8));
 template <typename T>
 constexpr bool kStepNarrow = !std::is_same<T, float>::value;
 
@@ -56,7 +59,7 @@ constexpr bool kStepNarrow = !std::is_same<T, float>::value;
 // before either collides, which doubles the bytes a wavefront has in flight.
 // nb_bulk then counts block pairs.  Only the full step (blk0 = 0) uses it.
 template <typename T, bool POROUS, bool NARROW, int SPT = 1>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kStepWaves<T, SPT>, 8))) void k_step(
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kStepWaves<T, SPT, NARROW>, 8))) void k_step(
     const T *__restrict__ A, T *__restrict__ B, GatherArgs a, const int32_t *__restrict__ order, int64_t n0,
     int64_t nb_io, int64_t blk0, int64_t nb_bulk, int xcd_chunk, typename Acc<T>::type omega, double *acc) {
   using C = typename Acc<T>::type;
