@@ -155,6 +155,7 @@ def run_storage(g, tables, tau, storage, steps, warmup, scheme="pull", windkesse
     achieved = bpl * n / (st["kernel_ms"] * 1e-3) / 1e9
     order = {v: k for k, v in hlb.ORDER.items()}[info["order"]]
     return dict(storage=storage, n_sites=n, bytes_per_lup=bpl, ms_per_step=dt / steps * 1e3, order=order,
+                xcd_remap=info["xcd_remap"],
                 mlups=mlups, alg_gbs=bpl * n * steps / dt / 1e9, kernel_ms=st["kernel_ms"],
                 event_step_ms=st["step_ms"], kernel_gbs=achieved,
                 frac=achieved / PEAK_GBS, mass=m, mass_residual_rel=r / m)
@@ -560,7 +561,8 @@ def main():
         "dtype": {"f64": "f64", "f32": "f32-storage", "f16": "f16-storage"}[main_st],
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {desc}; {g.n} fluid sites, tau {tau}, storage {main_st}",
-                   "n_sites": g.n, "storage": main_st, "order": R["order"], "parallelism": "single GPU"},
+                   "n_sites": g.n, "storage": main_st, "order": R["order"], "xcd_remap": R["xcd_remap"],
+                   "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(R["kernel_gbs"], 1), "peak": PEAK_GBS, "unit": "GB/s",
                      "frac": round(R["frac"], 4), "traffic": traffic,
                      "kernel": "k_step (all site groups, one launch per step)",

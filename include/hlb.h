@@ -120,8 +120,13 @@ typedef struct {
   int32_t storage;     /* hlb_storage (default HLB_F64) */
   int32_t order;       /* hlb_order (default HLB_ORDER_LEX) */
   int32_t xcd_remap;   /* K > 0: renumber the bulk kernel's workgroups so that
-                          each of the 8 XCDs gets K consecutive tiles of every
-                          window of 8K tiles (default 8); 0: plain block order */
+                          each of the 8 XCDs gets K consecutive 256-position
+                          blocks of every window of 8K blocks; 0: plain block
+                          order; -1 (default): chosen by the library from the
+                          storage and the buffer size (FP16 0; FP64 64, or 256
+                          when a population buffer exceeds 4 GiB; FP32 8, or
+                          128); hlb_info reports the value in use.  Results do
+                          not depend on it. */
   int32_t adjoint;     /* 1: enable hlb_adjoint_run (FP64 storage, pull
                           scheme; its buffers are allocated at the first run);
                           default 0 */
@@ -289,6 +294,7 @@ typedef struct {
   int32_t scheme;           /* hlb_scheme of the context */
   int32_t sites_per_thread; /* bulk+wall sites per thread of the full pull step */
   int32_t graph_steps;      /* steps per replayed graph in hlb_step (0: none) */
+  int32_t xcd_remap;        /* workgroup-to-XCD chunk in use (hlb_options.xcd_remap) */
 } hlb_info_t;
 hlb_status hlb_info(const hlb_ctx *ctx, hlb_info_t *info);
 

@@ -61,6 +61,18 @@ size_t storage_bytes(int storage) {
   return storage == HLB_F64 ? 8 : (storage == HLB_F32_SHIFTED ? 4 : 2);
 }
 
+// Workgroup-to-XCD chunk of the step kernel when the caller leaves it to
+// the library (hlb_options.xcd_remap = -1), from sweeps of the chunk (0 to
+// 4096 blocks) on the 2e7- and 2e8-site trees: FP16 runs fastest in plain
+// block order at both sizes; FP64 with 64 blocks per chunk while a
+// population buffer fits in 4 GiB and 256 above; FP32 with 8 and 128.
+int auto_xcd_chunk(int storage, int64_t np) {
+  const bool big = (uint64_t)Q * (uint64_t)np * storage_bytes(storage) > (uint64_t(1) << 32);
+  if (storage == HLB_F16_SHIFTED) return 0;
+  if (storage == HLB_F32_SHIFTED) return big ? 128 : 8;
+  return big ? 256 : 64;
+}
+
 // group of a site type: bulk and wall are merged (Sec. 3.2.2)
 inline int group_of(int type) {
   switch (type) {
@@ -429,7 +441,7 @@ hlb_status hlb_default_options(hlb_options *opt) {
   if (!opt) return fail(HLB_EINVAL, "null options");
   opt->storage = HLB_F64;
   opt->order = HLB_ORDER_LEX;
-  opt->xcd_remap = 8;
+  opt->xcd_remap = -1;
   opt->adjoint = 0;
   opt->rho0 = 1.0;
   opt->max_device_bytes = 0;
@@ -465,7 +477,7 @@ static hlb_status create_impl(int64_t n, const int32_t *coords, const uint8_t *t
   if (opt.ladd_rho_local && opt.adjoint)
     return fail(HLB_EINVAL, "the adjoint takes the Ladd rule with rho0 (ladd_rho_local must be 0)");
   if (!(opt.rho0 > 0.0) || !std::isfinite(opt.rho0)) return fail(HLB_EINVAL, "rho0 must be finite and > 0");
-  if ((opt.adjoint != 0 && opt.adjoint != 1) || opt.max_device_bytes < 0 || opt.xcd_remap < 0 ||
+  if ((opt.adjoint != 0 && opt.adjoint != 1) || opt.max_device_bytes < 0 || opt.xcd_remap < -1 ||
       opt.xcd_remap > (1 << 20))
     return fail(HLB_EINVAL, "bad options");
   if (opt.adjoint && opt.storage != HLB_F64) return fail(HLB_EINVAL, "the adjoint needs FP64 storage");
@@ -630,6 +642,7 @@ static hlb_status create_impl(int64_t n, const int32_t *coords, const uint8_t *t
   L.io_begin = L.gbeg[1];
   L.nio = L.np - L.io_begin;
   const int64_t np = L.np;
+  if (opt.xcd_remap < 0) c->cfg.xcd_chunk = auto_xcd_chunk(opt.storage, np);
   c->order_host.assign(np, -1);
   std::vector<int32_t> inv(n);
   for (int g = 0; g < kGroups; ++g)
@@ -1483,6 +1496,7 @@ hlb_status hlb_info(const hlb_ctx *c, hlb_info_t *info) {
   info->scheme = c->cfg.scheme;
   info->sites_per_thread = c->cfg.sites_per_thread;
   info->graph_steps = c->graph_steps;
+  info->xcd_remap = c->cfg.xcd_chunk;
   info->device_bytes = c->dev_bytes;
   return HLB_OK;
 }

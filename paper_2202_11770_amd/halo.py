@@ -112,7 +112,7 @@ _DTYPE = {"f64": "float64", "f32": "float32", "f16": "float16"}
 class SplitSimulation:
     """One context per part on one GPU; see the module docstring."""
 
-    def __init__(self, geom, tau: float, storage: str = "f64", tables=None, nparts: int = 2, xcd_remap: int = 8,
+    def __init__(self, geom, tau: float, storage: str = "f64", tables=None, nparts: int = 2, xcd_remap: int = -1,
                  shared_stream: bool = False, exchange: str = "direct"):
         """shared_stream: all parts' updates on one stream (their kernels run
         back to back) instead of one stream per part (they may overlap); the

@@ -63,7 +63,7 @@ class hlb_info_t(ctypes.Structure):
                 ("device_bytes", ctypes.c_int64), ("table_bytes_per_site", ctypes.c_double),
                 ("n_segments", ctypes.c_int64), ("n_iolets", ctypes.c_int64), ("adjoint", ctypes.c_int32),
                 ("porous", ctypes.c_int32), ("scheme", ctypes.c_int32), ("sites_per_thread", ctypes.c_int32),
-                ("graph_steps", ctypes.c_int32)]
+                ("graph_steps", ctypes.c_int32), ("xcd_remap", ctypes.c_int32)]
 
 
 class hlb_stats_t(ctypes.Structure):
@@ -362,7 +362,7 @@ def hlb_info(ctx) -> dict:
                 order=i.order, bytes_per_lup=i.bytes_per_lup, device_bytes=i.device_bytes,
                 table_bytes_per_site=i.table_bytes_per_site, n_segments=i.n_segments, n_iolets=i.n_iolets,
                 adjoint=i.adjoint, porous=i.porous, scheme=i.scheme, sites_per_thread=i.sites_per_thread,
-                graph_steps=i.graph_steps)
+                graph_steps=i.graph_steps, xcd_remap=i.xcd_remap)
 
 
 def hlb_macros(ctx, want=("rho", "u", "wss")):
@@ -525,7 +525,7 @@ class Simulation:
     iolet_kinds: list = None
 
     @classmethod
-    def create(cls, geom, tau: float, storage: str = "f64", order: str | None = None, xcd_remap: int = 8,
+    def create(cls, geom, tau: float, storage: str = "f64", order: str | None = None, xcd_remap: int = -1,
                rho0: float = 1.0, max_device_bytes: int = 0, tables=None, adjoint: bool = False,
                scheme: str = "pull", sites_per_thread: int = 0, graph_steps: int = 0, order_block: int = 0,
                ladd_rho_local: bool = False):

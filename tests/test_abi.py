@@ -35,7 +35,7 @@ def test_exports_every_declared_symbol():
 
 def test_default_options():
     o = hlb.hlb_default_options()
-    assert (o.storage, o.order, o.xcd_remap, o.adjoint, o.rho0, o.max_device_bytes) == (0, 1, 8, 0, 1.0, 0)
+    assert (o.storage, o.order, o.xcd_remap, o.adjoint, o.rho0, o.max_device_bytes) == (0, 1, -1, 0, 1.0, 0)
     assert (o.scheme, o.sites_per_thread, o.graph_steps, o.order_block) == (hlb.HLB_SCHEME_PULL, 0, 0, 6)
     assert o.ladd_rho_local == 0
 
@@ -137,6 +137,10 @@ def test_rejects_bad_options(cyl):
     o = hlb.hlb_default_options()
     o.order = 6
     _expect(hlb.HLB_EINVAL, hlb.hlb_create, cyl.coords, cyl.types, cyl.nbr, 0.8, cyl.iolets, o, match="order")
+    for bad in (-2, (1 << 20) + 1):
+        o = hlb.hlb_default_options()
+        o.xcd_remap = bad
+        _expect(hlb.HLB_EINVAL, hlb.hlb_create, cyl.coords, cyl.types, cyl.nbr, 0.8, cyl.iolets, o)
     o = hlb.hlb_default_options()
     o.ladd_rho_local = 2
     _expect(hlb.HLB_EINVAL, hlb.hlb_create, cyl.coords, cyl.types, cyl.nbr, 0.8, cyl.iolets, o, match="ladd_rho_local")
