@@ -79,6 +79,8 @@ def _declare_adjoint(lib):
     P, i64, i32, d = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
     lib.orc_adj_run.argtypes = [i64, P, P, d, d, P, i32, P, i64, i64, i64, i64, i32, P, P, P, P, P, P]
     lib.orc_adj_run.restype = ctypes.c_int
+    lib.orc_adj_run_wk.argtypes = [i64, P, P, d, d, P, i32, P, i64, i64, i64, i64, i32, P, P, P, P, P, P, P, P]
+    lib.orc_adj_run_wk.restype = ctypes.c_int
     lib.orc_tl_run.argtypes = [i64, P, P, d, d, P, i32, P, i64, i64, i64, i64, i32, P, P, P, P, P, P]
     lib.orc_tl_run.restype = ctypes.c_int
     lib.orc_iolet_flux.argtypes = [i64, P, P, d, d, P, i32, i64, P, P]
@@ -168,7 +170,8 @@ class Problem:
     def wss_sum(self, f) -> float:
         return float(_load().orc_wss_sum(self.n, _p(self.nbr), self.tau, _p(np.ascontiguousarray(f))))
 
-    def adjoint(self, f0, t0: int, nsteps: int, obj_t0: int, obj_t1: int, weights=None, state_grad=False):
+    def adjoint(self, f0, t0: int, nsteps: int, obj_t0: int, obj_t1: int, weights=None, state_grad=False,
+                windkessel=None):
         """Reference adjoint (oracle_adjoint.c).  J = sum over t in (obj_t0,
         obj_t1] of the summed wall shear stress (weights None), or of
         sum_k weights[k] Q_k(t), Q_k(t) the outflow of iolet k during the
@@ -176,7 +179,10 @@ class Problem:
         respect to the per-step iolet table values [n_io][nsteps] (amplitude
         or ghost density) and the per-site porosity [n], and with
         state_grad also the derivative with respect to f0 [n][19].  Keeps all
-        nsteps+1 states in memory."""
+        nsteps+1 states in memory.  windkessel maps pressure iolets to
+        (rho_ref, R1, C, R2, X0) as in run_windkessel; their densities then
+        come from that model, and their table-value derivatives are those
+        with respect to the density held at each step."""
         if self.ladd_rho_local:
             raise ValueError("the reference adjoint takes the Ladd rule with rho0")
         f0 = np.ascontiguousarray(f0, dtype=np.float64)
@@ -185,10 +191,22 @@ class Problem:
         dphi = np.zeros(self.n)
         w = None if weights is None else np.ascontiguousarray(weights, dtype=np.float64)
         df0 = np.zeros_like(f0) if state_grad else None
-        rc = _load().orc_adj_run(self.n, _p(self.coords), _p(self.nbr), self.tau, self.rho0, ctypes.byref(self.io),
-                                 self.n_io, _p(self.phi), int(t0), int(nsteps), int(obj_t0), int(obj_t1),
-                                 0 if w is None else 1, None if w is None else _p(w), _p(f0),
-                                 _p(J), _p(dA), _p(dphi), _p(df0))
+        if windkessel:
+            on = np.zeros(max(self.n_io, 1), dtype=np.int32)
+            par = np.zeros((max(self.n_io, 1), 5))
+            for k, m in windkessel.items():
+                on[k] = 1
+                par[k] = m
+            rc = _load().orc_adj_run_wk(self.n, _p(self.coords), _p(self.nbr), self.tau, self.rho0,
+                                        ctypes.byref(self.io), self.n_io, _p(self.phi), int(t0), int(nsteps),
+                                        int(obj_t0), int(obj_t1), 0 if w is None else 1,
+                                        None if w is None else _p(w), _p(on), _p(par), _p(f0),
+                                        _p(J), _p(dA), _p(dphi), _p(df0))
+        else:
+            rc = _load().orc_adj_run(self.n, _p(self.coords), _p(self.nbr), self.tau, self.rho0,
+                                     ctypes.byref(self.io), self.n_io, _p(self.phi), int(t0), int(nsteps),
+                                     int(obj_t0), int(obj_t1), 0 if w is None else 1, None if w is None else _p(w),
+                                     _p(f0), _p(J), _p(dA), _p(dphi), _p(df0))
         if rc != 0:
             raise ValueError("oracle adjoint failed")
         if state_grad:
@@ -254,17 +272,32 @@ class Problem:
                 st[k] = [X, rho_ref + R1 * Q[k] + X, Q[k]]
         return {k: (v[1], v[0], v[2]) for k, v in st.items()}
 
-    def objective(self, f0, t0: int, nsteps: int, obj_t0: int, obj_t1: int, weights=None) -> float:
-        """J of adjoint() by a plain forward run (no derivatives)."""
+    def objective(self, f0, t0: int, nsteps: int, obj_t0: int, obj_t1: int, weights=None,
+                  windkessel=None) -> float:
+        """J of adjoint() by a plain forward run (no derivatives); windkessel
+        as in adjoint() (the outlets' tables are put back afterwards)."""
         f = np.array(f0, dtype=np.float64, copy=True)
+        wk = dict(windkessel or {})
+        saved = {k: self._tables[k].copy() for k in wk}
+        st = {k: [m[4], m[0] + m[4]] for k, m in wk.items()}  # X, rho
         J = 0.0
         for s in range(nsteps):
             t = t0 + s + 1
-            if weights is not None and obj_t0 < t <= obj_t1:
-                J += float(np.dot(weights, self.iolet_flux(f, t - 1)))
+            for k in wk:
+                self.set_table(k, [st[k][1]])
+            flux_here = weights is not None and obj_t0 < t <= obj_t1
+            Q = self.iolet_flux(f, t - 1) if (flux_here or wk) else None
+            if flux_here:
+                J += float(np.dot(weights, Q))
             self.run(f, t0 + s, 1)
             if weights is None and obj_t0 < t <= obj_t1:
                 J += self.wss_sum(f)
+            for k, (rho_ref, R1, C, R2, _) in wk.items():
+                X = st[k][0]
+                X = X + (Q[k] - (X / R2 if R2 > 0 else 0.0)) / C if C > 0 else R2 * Q[k]
+                st[k] = [X, rho_ref + R1 * Q[k] + X]
+        for k, tab in saved.items():
+            self.set_table(k, tab)
         return J
 
     def collide_all(self, f) -> np.ndarray:

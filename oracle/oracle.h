@@ -24,11 +24,12 @@
  * and the adjoint and tangent-linear models of oracle_adjoint.c and
  * oracle_tangent.c.
  *
- * Pins: see tests/test_oracle_*.py.  The velocity-iolet density choice
- * (reference density rho0), the pressure-iolet ghost velocity (site velocity
- * projected on the iolet normal) and the wall normal used by the shear stress
- * are readings with no physical pin: parity unpinned for those three choices
- * beyond both codes implementing the written definition.
+ * Pins: see tests/test_oracle_*.py.  The pressure-iolet ghost velocity
+ * (site velocity projected on the iolet normal) and the wall normal used by
+ * the shear stress are readings with no physical pin: parity unpinned for
+ * those two choices beyond both codes implementing the written definition.
+ * The velocity-iolet density (reference density rho0, or the site's own
+ * density with rho_local set) is pinned by a Couette column away from rho0.
  */
 #ifndef HLB_ORACLE_H
 #define HLB_ORACLE_H
@@ -128,6 +129,21 @@ int orc_adj_run(int64_t n, const int32_t *coords, const int32_t *nbr, double tau
                 const orc_iolet *io, int32_t n_io, const double *phi, int64_t t0, int64_t nsteps,
                 int64_t obj_t0, int64_t obj_t1, int32_t objective, const double *weights, const double *f0,
                 double *J, double *dJ_dtab, double *dJ_dphi, double *dJ_df0);
+
+/* orc_adj_run with Windkessel outlets (an extension): pressure iolet k with
+ * wk_on[k] != 0 takes its density from a three-element model instead of its
+ * table, wk[5k..5k+4] = (rho_ref, R1, C, R2, X0) (C >= 0): after the update
+ * s -> s+1, whose outflow is Q,
+ *   X(s+1) = X(s) + (Q - X/R2)/C (C > 0; no X/R2 term if R2 = 0), R2 Q (C = 0),
+ *   rho_k(s+1) = rho_ref + R1 Q + X(s+1),  X(0) = X0, rho_k(0) = rho_ref + X0.
+ * dJ_dtab of such an outlet is the derivative with respect to the density it
+ * held at each step.  Returns -1 if a flagged iolet is not a pressure iolet
+ * or has C < 0. */
+int orc_adj_run_wk(int64_t n, const int32_t *coords, const int32_t *nbr, double tau, double rho0,
+                   const orc_iolet *io, int32_t n_io, const double *phi, int64_t t0, int64_t nsteps,
+                   int64_t obj_t0, int64_t obj_t1, int32_t objective, const double *weights, const int32_t *wk_on,
+                   const double *wk, const double *f0, double *J, double *dJ_dtab, double *dJ_dphi,
+                   double *dJ_df0);
 
 /* Tangent-linear model (oracle_tangent.c): the derivative dJ of the
  * objective of orc_adj_run (same arguments) in the direction given by df0

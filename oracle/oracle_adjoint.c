@@ -193,56 +193,103 @@ static int adj_step(int64_t n, const int32_t *coords, const int32_t *nbr, double
   return bad ? -1 : 0;
 }
 
-int orc_adj_run(int64_t n, const int32_t *coords, const int32_t *nbr, double tau, double rho0,
-                const orc_iolet *io, int32_t n_io, const double *phi, int64_t t0, int64_t nsteps,
-                int64_t obj_t0, int64_t obj_t1, int32_t objective, const double *weights, const double *f0,
-                double *J, double *dJ_dA, double *dJ_dphi, double *dJ_df0) {
+/* Windkessel outlets (an extension; the forward model is the oracle's
+ * Python driver, Problem.run_windkessel): pressure iolet k with wk_on[k] set
+ * takes at step s the density rho_k(s) of its state, and after the update
+ * s -> s+1 with outflow Q_k(s) (orc_iolet_flux at s)
+ *   X(s+1)     = X(s) + (Q - X/R2)/C   (C > 0; no X/R2 term if R2 = 0),
+ *                R2 Q                   (C = 0),
+ *   rho_k(s+1) = rho_ref + R1 Q + X(s+1),
+ * from X(0) = X0, rho_k(0) = rho_ref + X0; wk[k] = (rho_ref, R1, C, R2, X0).
+ * Its adjoint is a scalar recurrence per outlet, backwards in s:
+ *   LX(s+1) = Lr(s+1) + kappa LX(s+2),  kappa = dX(s+2)/dX(s+1)
+ *             (1 - 1/(R2 C), 1 if R2 = 0, 0 if C = 0),
+ *   dJ/dQ_k(s) = R1 Lr(s+1) + dX(s+1)/dQ LX(s+1)   (1/C, or R2 if C = 0),
+ * Lr(s) the derivative with respect to the density used at step s (the
+ * table-value derivative of that step, which already carries the outflow
+ * weights of step s), Lr(N) = LX(N) = LX(N+1) = 0.  dJ/dQ_k(s) enters the
+ * adjoint step of the update s -> s+1 as an outflow weight, added to the
+ * objective's own weight. */
+static int adj_run(int64_t n, const int32_t *coords, const int32_t *nbr, double tau, double rho0,
+                   const orc_iolet *io, int32_t n_io, const double *phi, int64_t t0, int64_t nsteps,
+                   int64_t obj_t0, int64_t obj_t1, int32_t objective, const double *weights,
+                   const int32_t *wk_on, const double *wk, const double *f0, double *J, double *dJ_dA,
+                   double *dJ_dphi, double *dJ_df0) {
   if (objective != 0 && (objective != 1 || (n_io > 0 && !weights))) return -1;
+  int any_wk = 0;
+  for (int k = 0; wk_on && k < n_io; ++k) {
+    if (!wk_on[k]) continue;
+    if (io[k].kind != 1 || !wk || wk[5 * k + 2] < 0.0) return -1;
+    any_wk = 1;
+  }
   const int wss = objective == 0;
   lattice_init();
   const size_t sz = (size_t)ORC_Q * (size_t)n;
+  const size_t nk = n_io > 0 ? (size_t)n_io : 1;
   double *F = (double *)malloc(sizeof(double) * sz * (size_t)(nsteps + 1));
   double *mu = (double *)calloc(sz, sizeof(double));
   double *mu2 = (double *)calloc(sz, sizeof(double));
   double *gr = (double *)malloc(sizeof(double) * sz);
-  double *dA = (double *)calloc(n_io > 0 ? (size_t)n_io : 1, sizeof(double));
-  if (!F || !mu || !mu2 || !gr || !dA) {
-    free(F); free(mu); free(mu2); free(gr); free(dA);
-    return -1;
-  }
-  memcpy(F, f0, sizeof(double) * sz);
-  for (int64_t s = 0; s < nsteps; ++s)
-    if (orc_step(n, coords, nbr, tau, rho0, io, n_io, phi, t0 + s, F + sz * s, F + sz * (s + 1), NULL, NULL) != 0) {
-      free(F); free(mu); free(mu2); free(gr); free(dA);
-      return -1;
+  double *dA = (double *)calloc(nk, sizeof(double));
+  double *Qk = (double *)calloc(nk, sizeof(double));
+  double *weff = (double *)calloc(nk, sizeof(double));
+  double *Lr = (double *)calloc(nk, sizeof(double));  /* Lr(s+1) */
+  double *LX = (double *)calloc(nk, sizeof(double));  /* LX(s+2), then LX(s+1) */
+  double *rh = (double *)calloc(nk * (size_t)(nsteps + 1), sizeof(double)); /* rho_k(s) */
+  orc_iolet *iw = (orc_iolet *)malloc(sizeof(orc_iolet) * nk);
+  int rc = -1;
+  if (!F || !mu || !mu2 || !gr || !dA || !Qk || !weff || !Lr || !LX || !rh || !iw) goto done;
+  if (n_io > 0) memcpy(iw, io, sizeof(orc_iolet) * (size_t)n_io);
+#define WK_AT(s)                                                             \
+  for (int k = 0; any_wk && k < n_io; ++k)                                   \
+    if (wk_on[k]) {                                                          \
+      iw[k].table = rh + (size_t)k * (size_t)(nsteps + 1) + (size_t)(s);    \
+      iw[k].table_len = 1;                                                   \
     }
+  /* forward, storing every state (and the outlets' densities) */
+  {
+    double *X = Lr; /* the outlets' X during the forward sweep (reset below) */
+    for (int k = 0; any_wk && k < n_io; ++k)
+      if (wk_on[k]) {
+        X[k] = wk[5 * k + 4];
+        rh[(size_t)k * (size_t)(nsteps + 1)] = wk[5 * k] + wk[5 * k + 4];
+      }
+    memcpy(F, f0, sizeof(double) * sz);
+    for (int64_t s = 0; s < nsteps; ++s) {
+      WK_AT(s);
+      if (any_wk && orc_iolet_flux(n, coords, nbr, tau, rho0, iw, n_io, t0 + s, F + sz * s, Qk) != 0) goto done;
+      if (orc_step(n, coords, nbr, tau, rho0, iw, n_io, phi, t0 + s, F + sz * s, F + sz * (s + 1), NULL, NULL) != 0)
+        goto done;
+      for (int k = 0; any_wk && k < n_io; ++k) {
+        if (!wk_on[k]) continue;
+        const double *P = wk + 5 * k;
+        X[k] = P[2] > 0.0 ? X[k] + (Qk[k] - (P[3] > 0.0 ? X[k] / P[3] : 0.0)) / P[2] : P[3] * Qk[k];
+        rh[(size_t)k * (size_t)(nsteps + 1) + (size_t)(s + 1)] = P[0] + P[1] * Qk[k] + X[k];
+      }
+    }
+    for (size_t k = 0; k < nk; ++k) Lr[k] = 0.0;
+  }
   /* objective: WSS of the state at t, or the weighted outflow of the update
    * t-1 -> t, for each t in the window */
-  double Jsum = 0.0, Jc = 0.0;
-  double *Qk = (double *)calloc(n_io > 0 ? (size_t)n_io : 1, sizeof(double));
-  if (!Qk) {
-    free(F); free(mu); free(mu2); free(gr); free(dA);
-    return -1;
-  }
-  for (int64_t s = 1; s <= nsteps; ++s) {
-    const int64_t t = t0 + s;
-    if (t <= obj_t0 || t > obj_t1) continue;
-    double v = 0.0;
-    if (wss) {
-      v = orc_wss_sum(n, nbr, tau, F + sz * s);
-    } else {
-      if (orc_iolet_flux(n, coords, nbr, tau, rho0, io, n_io, t - 1, F + sz * (s - 1), Qk) != 0) {
-        free(F); free(mu); free(mu2); free(gr); free(dA); free(Qk);
-        return -1;
+  {
+    double Jsum = 0.0, Jc = 0.0;
+    for (int64_t s = 1; s <= nsteps; ++s) {
+      const int64_t t = t0 + s;
+      if (t <= obj_t0 || t > obj_t1) continue;
+      double v = 0.0;
+      if (wss) {
+        v = orc_wss_sum(n, nbr, tau, F + sz * s);
+      } else {
+        WK_AT(s - 1);
+        if (orc_iolet_flux(n, coords, nbr, tau, rho0, iw, n_io, t - 1, F + sz * (s - 1), Qk) != 0) goto done;
+        for (int k = 0; k < n_io; ++k) v += weights[k] * Qk[k];
       }
-      for (int k = 0; k < n_io; ++k) v += weights[k] * Qk[k];
+      const double y = v - Jc, tt = Jsum + y;
+      Jc = (tt - Jsum) - y;
+      Jsum = tt;
     }
-    const double y = v - Jc, tt = Jsum + y;
-    Jc = (tt - Jsum) - y;
-    Jsum = tt;
+    *J = Jsum;
   }
-  free(Qk);
-  *J = Jsum;
   if (dJ_dphi) memset(dJ_dphi, 0, sizeof(double) * (size_t)n);
   if (dJ_dA) memset(dJ_dA, 0, sizeof(double) * (size_t)(n_io > 0 ? n_io : 0) * (size_t)nsteps);
   /* mu = dJ/df_T */
@@ -254,11 +301,19 @@ int orc_adj_run(int64_t n, const int32_t *coords, const int32_t *nbr, double tau
     for (int k = 0; k < n_io; ++k) dA[k] = 0.0;
     /* the outflow of the update t0+s -> t0+s+1 counts if t0+s+1 is in the window */
     const int flux_here = !wss && t0 + s + 1 > obj_t0 && t0 + s + 1 <= obj_t1;
-    if (adj_step(n, coords, nbr, tau, rho0, io, n_io, phi, t0 + s, F + sz * s, mu, flux_here ? weights : NULL, mu2,
-                 dA, dJ_dphi) != 0) {
-      free(F); free(mu); free(mu2); free(gr); free(dA);
-      return -1;
+    for (int k = 0; k < n_io; ++k) weff[k] = flux_here ? weights[k] : 0.0;
+    for (int k = 0; any_wk && k < n_io; ++k) {
+      if (!wk_on[k]) continue;
+      const double *P = wk + 5 * k;
+      const double kappa = P[2] > 0.0 ? 1.0 - (P[3] > 0.0 ? 1.0 / (P[3] * P[2]) : 0.0) : 0.0;
+      LX[k] = Lr[k] + kappa * LX[k];
+      weff[k] += P[1] * Lr[k] + (P[2] > 0.0 ? 1.0 / P[2] : P[3]) * LX[k];
     }
+    WK_AT(s);
+    if (adj_step(n, coords, nbr, tau, rho0, iw, n_io, phi, t0 + s, F + sz * s, mu,
+                 (flux_here || any_wk) ? weff : NULL, mu2, dA, dJ_dphi) != 0)
+      goto done;
+    for (int k = 0; k < n_io; ++k) Lr[k] = dA[k];
     if (dJ_dA)
       for (int k = 0; k < n_io; ++k) dJ_dA[(size_t)k * nsteps + s] = dA[k];
     const int64_t t = t0 + s;
@@ -273,7 +328,26 @@ int orc_adj_run(int64_t n, const int32_t *coords, const int32_t *nbr, double tau
     mu = mu2;
     mu2 = tmp;
   }
+#undef WK_AT
   if (dJ_df0) memcpy(dJ_df0, mu, sizeof(double) * sz);
-  free(F); free(mu); free(mu2); free(gr); free(dA);
-  return 0;
+  rc = 0;
+done:
+  free(F); free(mu); free(mu2); free(gr); free(dA); free(Qk); free(weff); free(Lr); free(LX); free(rh); free(iw);
+  return rc;
+}
+
+int orc_adj_run(int64_t n, const int32_t *coords, const int32_t *nbr, double tau, double rho0,
+                const orc_iolet *io, int32_t n_io, const double *phi, int64_t t0, int64_t nsteps,
+                int64_t obj_t0, int64_t obj_t1, int32_t objective, const double *weights, const double *f0,
+                double *J, double *dJ_dA, double *dJ_dphi, double *dJ_df0) {
+  return adj_run(n, coords, nbr, tau, rho0, io, n_io, phi, t0, nsteps, obj_t0, obj_t1, objective, weights, NULL,
+                 NULL, f0, J, dJ_dA, dJ_dphi, dJ_df0);
+}
+
+int orc_adj_run_wk(int64_t n, const int32_t *coords, const int32_t *nbr, double tau, double rho0,
+                   const orc_iolet *io, int32_t n_io, const double *phi, int64_t t0, int64_t nsteps,
+                   int64_t obj_t0, int64_t obj_t1, int32_t objective, const double *weights, const int32_t *wk_on,
+                   const double *wk, const double *f0, double *J, double *dJ_dA, double *dJ_dphi, double *dJ_df0) {
+  return adj_run(n, coords, nbr, tau, rho0, io, n_io, phi, t0, nsteps, obj_t0, obj_t1, objective, weights, wk_on, wk,
+                 f0, J, dJ_dA, dJ_dphi, dJ_df0);
 }

@@ -29,6 +29,7 @@ COUETTE_RHO = FLOWS + "::test_couette_ladd_density"
 PIPE = FLOWS + "::test_cylinder_poiseuille"
 DUCT = FLOWS + "::test_duct_pressure_poiseuille"
 POROUS = FLOWS + "::test_porous_box_relaxes_to_reservoir"
+WKADJ = "tests/test_oracle_windkessel_adjoint.py"
 DOT = TAN + "::test_dot_product_identity"
 TLFD = TAN + "::test_tangent_vs_central_differences"
 
@@ -86,6 +87,12 @@ MUTANTS = [
     # adjoint: the outflow's direct term at Ladd links with the wrong sign
     ("adj_flux_ladd", "oracle_adjoint.c", "myA[k] += (m - wk) * (-2.0 * LW[i]", "myA[k] += (m + wk) * (-2.0 * LW[i]",
      [DOT, ADJ]),
+    # adjoint through a Windkessel outlet: the capacitor's 1/C dropped from
+    # dX(s+1)/dQ(s); the leak's decay of X taken with the wrong sign
+    ("adj_wk_capacitance", "oracle_adjoint.c", "(P[2] > 0.0 ? 1.0 / P[2] : P[3]) * LX[k]",
+     "(P[2] > 0.0 ? 1.0 : P[3]) * LX[k]", [WKADJ]),
+    ("adj_wk_leak_sign", "oracle_adjoint.c", "1.0 - (P[3] > 0.0 ? 1.0 / (P[3] * P[2]) : 0.0)",
+     "1.0 + (P[3] > 0.0 ? 1.0 / (P[3] * P[2]) : 0.0)", [WKADJ]),
     # tangent: velocity derivative without the density term
     ("tan_velocity", "oracle_tangent.c", "du[a] = (dj[a] - dr * u[a]) / r;", "du[a] = dj[a] / r;", [TLFD]),
     # tangent: porous-wall derivative with the wrong sign
@@ -112,7 +119,7 @@ def _run_pins(tmp_path, edit, pins):
 
 
 def test_unaltered_copy_passes_the_pins(tmp_path):
-    r = _run_pins(tmp_path, None, [ALG, FLOWS, ADJ, TAN])
+    r = _run_pins(tmp_path, None, [ALG, FLOWS, ADJ, TAN, WKADJ])
     print(r.stdout[-2000:])
     assert r.returncode == 0
 
