@@ -329,7 +329,9 @@ hlb_status hlb_stats(hlb_ctx *ctx, hlb_stats_t *stats);
  * state advanced by one small kernel after it.  rho_k starts at rho_ref + X0.
  * w = NULL turns the model off (the iolet keeps its last table);
  * hlb_set_iolet_table on the iolet also turns it off.  R1, C, R2 >= 0 and,
- * if C > 0 and R2 > 0, R2 C >= 1.  Not with hlb_adjoint_run or a partition.
+ * if C > 0 and R2 > 0, R2 C >= 1.  Not on a partition.  hlb_adjoint_run
+ * carries the model through its sweeps (its checkpoints hold the model's
+ * state).
  * hlb_windkessel_state: the density the next update uses, X and the last
  * update's outflow (synchronises).  State files and snapshots do not
  * include the model's state. */
@@ -439,7 +441,8 @@ hlb_status hlb_set_objective(hlb_ctx *ctx, int32_t kind, const double *weights);
  *   dJ_dA   [n_iolets][n] (host, may be NULL): the table value iolet k uses
  *           in the update t0+s -> t0+s+1: the amplitude A_k(t0 + s) of a
  *           velocity iolet, the ghost density rho_k(t0 + s) of a pressure
- *           iolet;
+ *           iolet (of a Windkessel outlet: the density its model gave it
+ *           for that update, the model's later response to it included);
  *   dJ_dphi [n_sites] (host, caller order, may be NULL): each site's
  *           porosity (hlb_set_porosity), zero at sites without wall links,
  *           evaluated at the current porosity (0 if none is set).

@@ -30,6 +30,9 @@ struct AdjBuffers {
   int64_t n_blist_wall = 0;   // leading entries below the iolet groups (wall links only)
   int32_t objective = HLB_OBJ_WSS;
   double *w = nullptr;        // [n_iolets] iolet-flux weights (device)
+  int32_t n_io = 0;           // iolets
+  double *wq = nullptr;       // [n_iolets] outflow weights of the reverse step in flight
+  double *lamX = nullptr;     // [n_iolets] adjoint of the Windkessel outlets' X
 };
 // Adjoint of the update (t-1 -> t): buffer `src` holds s_{t-1}; b.mu holds
 // mu_t on entry and mu_{t-1} on return; accumulates J's partial sums (if
@@ -38,6 +41,9 @@ struct AdjBuffers {
 hipError_t launch_adjoint_step(const LaunchCfg &cfg, const Layout &L, const DevPtrs &d, int src, int64_t t,
                                const AdjBuffers &b, int in_window, int64_t n_steps, int64_t step,
                                hipStream_t s);
+// The outflow weights b.wq of the reverse step of the update
+// t0 + step -> t0 + step + 1 (run first in each reverse step by
+// launch_adjoint_step; b.lamX must be zero before the sweep's first step).
 // J[0] := sum of the partial sums J[8, 8 + kAdjJSlots) (one workgroup).
 hipError_t launch_adjoint_objective(double *J, hipStream_t s);
 

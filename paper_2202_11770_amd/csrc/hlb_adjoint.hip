@@ -35,8 +35,17 @@ struct AdjArgs {
   double *dA;               // [n_io][n_steps]: iolet table-value derivatives
   double *dphi;             // [np], accumulated over the sweep
   int objective;            // HLB_OBJ_WSS or HLB_OBJ_IOLET_FLUX
-  const double *w;          // [n_io] iolet-flux weights
+  const double *w;          // [n_io] iolet-flux weights of the objective
+  // [n_io] outflow weights of this reverse step, dJ/dQ_k(t-1): the
+  // objective's inside its window plus a Windkessel outlet's model term
+  const double *wq;
 };
+
+// The value iolet k applies in the update a.t -> a.t+1: a Windkessel
+// outlet's density from its model state, else the table value.
+__device__ inline double iolet_value(const GatherArgs &a, const IoletDev &K, int k) {
+  return K.wk ? a.wk_rho[2 * k + (a.t & 1)] : a.tables[K.tab_off + a.t % K.tab_len];
+}
 
 // The wavefront's share s of the objective, added to its partial-sum slot
 // (one atomic per wavefront, spread over kAdjJSlots addresses); lane 0 adds.
@@ -259,8 +268,9 @@ __global__ __launch_bounds__(kBlock) void k_adj_collide(AdjArgs A) {
 //     (without porosity k_adj_collide takes the whole term, so the kernel
 //     then runs over the sites with iolet links alone);
 //   iolet table values: dJ/dA_k(t-1) += sum over links of k of (nu_i - w_k)
-//     d(fill_i)/dA_k, and with the iolet-flux objective J += w_k (leaving
-//     population - fill) per link.
+//     d(fill_i)/dA_k, w_k = dJ/dQ_k(t-1) the step's outflow weight, and with
+//     the iolet-flux objective J += (its weight) (leaving population - fill)
+//     per link.
 // It loads nu only at the site's wall and iolet links.  Compiled for 2
 // waves per SIMD: measured 2% faster per reverse step than the compiler's
 // default (4 waves) and than 1 or 3.
@@ -307,8 +317,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) 
         if (!(iol & (1u << (i - 1)))) continue;
         const int k = -a.nbr_io[(int64_t)(i - 1) * a.nio + (p - a.io_begin)] - 2;
         const IoletDev K = a.io[k];
-        const double val = a.tables[K.tab_off + a.t % K.tab_len];
-        const double wk = flux ? A.w[k] : 0.0;
+        const double val = iolet_value(a, K, k);
+        const double wk = A.wq[k];
+        const double wo = flux ? A.w[k] : 0.0;
         double coef, out;  // d(filled value)/d(table value); outflow of the link
         if (K.kind == HLB_IOLET_VELOCITY) {
           coef = a.corr[(int64_t)(i - 1) * a.nio + (p - a.io_begin)];
@@ -320,7 +331,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 2))) 
           out = A.S[pidx(p32, opp(i))] - val * coef;
         }
         dtab.add(A.dA + A.step, k, (m[i] - wk) * coef, A.n_steps);
-        q += wk * out;
+        q += wo * out;
       }
       if (flux) jsum = q;
     }
@@ -342,9 +353,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
   if (p >= a.np || A.order[p] < 0) return;
   const int32_t p32 = (int32_t)p;
   const double ph = POROUS ? a.phi[p] : 0.0;
-  // iolet-flux objective: a population leaving through a pressure iolet adds
-  // w_k to its own adjoint (the fill does not depend on it), and the fill's
-  // dependence on u enters with weight (nu - w_k)
+  // outflow weights w_k = dJ/dQ_k(t-1): a population leaving through a
+  // pressure iolet adds w_k to its own adjoint (the fill does not depend on
+  // it), and the fill's dependence on u enters with weight (nu - w_k)
   if (p < a.io_begin) {
     // bulk+wall group (block-uniform): fluid and wall links only, one load
     // per link as in the forward gather
@@ -368,7 +379,6 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
       __builtin_nontemporal_store((POROUS && ((walls >> i) & 1u)) ? (1.0 - ph) * v[i] : v[i], &A.mu[pidx(p32, i)]);
     return;
   }
-  const bool flux = A.objective == HLB_OBJ_IOLET_FLUX && A.in_window;
   // iolet groups: the site's 18 pull entries
   int32_t code[Q - 1];
 #pragma unroll
@@ -386,7 +396,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
     } else if (a.io[-c - 2].kind == HLB_IOLET_VELOCITY) {
       m[i] = A.nu[pidx(p32, opp(i))];
     } else {
-      m[i] = flux ? A.w[-c - 2] : 0.0;  // replaced by the ghost-density equilibrium
+      m[i] = A.wq[-c - 2];  // replaced by the ghost-density equilibrium
       pressure = true;
     }
   }
@@ -405,14 +415,14 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
       const IoletDev K = a.io[-c - 2];
       if (K.kind != HLB_IOLET_PRESSURE) continue;
       const int o = opp(i);  // incoming population = f^eq_o(rho_k, (u.n) n)
-      const double rk = a.tables[K.tab_off + a.t % K.tab_len];
+      const double rk = iolet_value(a, K, -c - 2);
       const double un = ux * K.n[0] + uy * K.n[1] + uz * K.n[2];
       const double gx = un * K.n[0], gy = un * K.n[1], gz = un * K.n[2];
       const double cu = cx(o) * gx + cy(o) * gy + cz(o) * gz;
       const double dx = wgt<double>(o) * rk * (3.0 * cx(o) + 9.0 * cu * cx(o) - 3.0 * gx);
       const double dy = wgt<double>(o) * rk * (3.0 * cy(o) + 9.0 * cu * cy(o) - 3.0 * gy);
       const double dz = wgt<double>(o) * rk * (3.0 * cz(o) + 9.0 * cu * cz(o) - 3.0 * gz);
-      const double wk = flux ? A.w[-c - 2] : 0.0;
+      const double wk = A.wq[-c - 2];
       const double coef = (A.nu[pidx(p32, o)] - wk) * (dx * K.n[0] + dy * K.n[1] + dz * K.n[2]) / rho;
 #pragma unroll
       for (int j = 0; j < Q; ++j)
@@ -421,6 +431,31 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
   }
 #pragma unroll
   for (int i = 0; i < Q; ++i) __builtin_nontemporal_store(m[i], &A.mu[pidx(p32, i)]);
+}
+
+// Outflow weights of the reverse step of the update s -> s+1 (s = step):
+// the objective's weight inside its window, plus, for a Windkessel outlet,
+// dJ/dQ_k(s) from the adjoint of its model (R19 of the readings):
+//   LX(s+1) = Lr(s+1) + kappa LX(s+2),  kappa = dX(s+2)/dX(s+1),
+//   dJ/dQ_k(s) = R1 Lr(s+1) + dX(s+1)/dQ LX(s+1),
+// Lr(s+1) = column s+1 of dA (the derivative with respect to the density of
+// step s+1, written by the previous reverse step), zero past the last step.
+// lamX holds LX(s+2) on entry and LX(s+1) on return.
+__global__ void k_adj_weights(const IoletDev *io, const WkParams *wk, int n_io, const double *dA,
+                              int64_t n_steps, int64_t step, const double *w, int flux, double *lamX,
+                              double *wq) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n_io) return;
+  double v = flux ? w[k] : 0.0;
+  if (wk && io[k].wk) {
+    const WkParams P = wk[k];
+    const double lr = step + 1 < n_steps ? dA[(int64_t)k * n_steps + step + 1] : 0.0;
+    const double kappa = P.C > 0.0 ? 1.0 - (P.R2 > 0.0 ? 1.0 / (P.R2 * P.C) : 0.0) : 0.0;
+    const double lx = lr + kappa * lamX[k];
+    v += P.R1 * lr + (P.C > 0.0 ? 1.0 / P.C : P.R2) * lx;
+    lamX[k] = lx;
+  }
+  wq[k] = v;
 }
 
 // J[0] := sum of the kAdjJSlots partial sums (one workgroup of kBlock).
@@ -463,6 +498,12 @@ hipError_t launch_adjoint_step(const LaunchCfg &cfg, const Layout &L, const DevP
   A.dphi = b.dphi;
   A.objective = b.objective;
   A.w = b.w;
+  A.wq = b.wq;
+  if (b.n_io > 0) {
+    if (!b.wq || !b.lamX) return hipErrorInvalidValue;
+    k_adj_weights<<<(b.n_io + 63) / 64, 64, 0, s>>>(d.io, d.wk, b.n_io, b.dA, n_steps, step, b.w,
+                                                    b.objective == HLB_OBJ_IOLET_FLUX && in_window, b.lamX, b.wq);
+  }
   const bool wss = b.objective == HLB_OBJ_WSS && in_window;
   const unsigned grid = blocks_of(L.np);
   if (cfg.porous) {

@@ -238,6 +238,10 @@ struct hlb_ctx {
   AdjBuffers adj;
   int64_t adj_dA_len = 0;
   std::vector<void *> adj_slots;  // checkpoint buffers (post-collision state)
+  // the Windkessel outlets' state per checkpoint slot: WkParams [n_iolets]
+  // then the densities [n_iolets][2]
+  void *adj_wk_slots = nullptr;
+  int64_t adj_wk_nslots = 0;
   // replayed step graphs (hlb_step): one per starting buffer, captured with
   // the time read from t_dev
   int graph_steps = 0;            // steps per graph; 0: no graphs
@@ -298,6 +302,10 @@ void free_all(hlb_ctx *c) {
   F(c->adj.mu); F(c->adj.nu); F(c->adj.J); F(c->adj.dA); F(c->adj.dphi); F(c->adj.w); F(c->adj.blist);
   for (void *q : c->adj_slots) F(q);
   c->adj_slots.clear();
+  F(c->adj_wk_slots);
+  c->adj_wk_slots = nullptr;
+  c->adj_wk_nslots = 0;
+  F(c->adj.wq); F(c->adj.lamX);
   c->adj = AdjBuffers();
   for (auto &ts : c->pool)
     for (auto &e : ts.e) (void)hipEventDestroy(e);
@@ -1752,6 +1760,7 @@ struct Revolve {
       void *dst = (last_dst && s == k - 1) ? last_dst : nullptr;
       if (dst) d.f[1 - c->cur] = dst;
       HIP_TRY(launch_step(c->cfg, c->L, d, c->cur, c->t, c->stream, nullptr, nullptr));
+      if (c->n_wk > 0) HIP_TRY(launch_windkessel(c->d, (int)c->iolets.size(), c->t, c->stream));
       in_slot = dst;
       c->cur = 1 - c->cur;
       c->t += 1;
@@ -1759,19 +1768,33 @@ struct Revolve {
     fwd += k;
     return HLB_OK;
   }
+  // the Windkessel outlets' state to (or from) checkpoint slot `slot`
+  hlb_status wk_state(int64_t slot, bool to_slot) {
+    if (c->n_wk <= 0) return HLB_OK;
+    const size_t nio = c->iolets.size(), pb = nio * sizeof(WkParams), rb = 2 * nio * sizeof(double);
+    char *base = static_cast<char *>(c->adj_wk_slots) + (size_t)slot * (pb + rb);
+    if (to_slot) {
+      HIP_TRY(hipMemcpyAsync(base, c->d.wk, pb, hipMemcpyDeviceToDevice, c->stream));
+      HIP_TRY(hipMemcpyAsync(base + pb, c->d.wk_rho, rb, hipMemcpyDeviceToDevice, c->stream));
+    } else {
+      HIP_TRY(hipMemcpyAsync(c->d.wk, base, pb, hipMemcpyDeviceToDevice, c->stream));
+      HIP_TRY(hipMemcpyAsync(c->d.wk_rho, base + pb, rb, hipMemcpyDeviceToDevice, c->stream));
+    }
+    return HLB_OK;
+  }
   hlb_status save(int64_t slot) {
     const void *src = in_slot ? in_slot : c->d.f[c->cur];
     if (src != c->adj_slots[slot])
       HIP_TRY(hipMemcpyAsync(c->adj_slots[slot], src, buf_bytes(c), hipMemcpyDeviceToDevice, c->stream));
     slot_t[slot] = c->t;
-    return HLB_OK;
+    return wk_state(slot, true);
   }
   hlb_status restore(int64_t slot) {
     in_slot = c->adj_slots[slot];
     c->cur = 0;
     c->t = slot_t[slot];
     c->direct = false;
-    return HLB_OK;
+    return wk_state(slot, false);
   }
   hlb_status adjoint_step(int64_t t) {  // needs the state of time t-1
     const int in_window = (t > w0 && t <= w1) ? 1 : 0;
@@ -1799,6 +1822,7 @@ struct Revolve {
       if (hlb_status st = restore(slot_a)) return st;
       if (hlb_status st = advance(m - a, c->adj_slots[slot_m])) return st;  // m - a >= 1
       slot_t[slot_m] = c->t;
+      if (hlb_status st = wk_state(slot_m, true)) return st;
       if (hlb_status st = reverse(m, b, slot_m, cfree - 1)) return st;
       b = m;
     }
@@ -1828,7 +1852,6 @@ namespace {
 hlb_status adjoint_sweep(hlb_ctx *c, int64_t n, int64_t obj_t0, int64_t obj_t1, int32_t n_snap,
                          int64_t *forward_steps) {
   if (n < 1 || n_snap < 1 || n_snap > 4096) return fail(HLB_EINVAL, "need n >= 1, 1 <= n_snap <= 4096");
-  if (c->n_wk > 0) return fail(HLB_ESTATE, "the adjoint does not cover Windkessel outlets");
   if (c->cfg.storage != HLB_F64 || !c->adj_on || c->cfg.scheme != HLB_SCHEME_PULL || c->cfg.ladd_local)
     return fail(HLB_ESTATE, "the adjoint needs FP64 storage and opt.adjoint = 1 at creation");
   if (hlb_status st = bind(c)) return st;
@@ -1844,6 +1867,24 @@ hlb_status adjoint_sweep(hlb_ctx *c, int64_t n, int64_t obj_t0, int64_t obj_t1, 
     // [0] the objective; [1, 5) the caller's flux accumulators while the sweep runs
     if (hlb_status st = dev_alloc(c, &p, kAdjJLen * sizeof(double))) return st;
     c->adj.J = static_cast<double *>(p);
+    if (hlb_status st = dev_alloc(c, &p, (size_t)std::max<int64_t>(1, nio) * sizeof(double))) return st;
+    c->adj.wq = static_cast<double *>(p);
+    if (hlb_status st = dev_alloc(c, &p, (size_t)std::max<int64_t>(1, nio) * sizeof(double))) return st;
+    c->adj.lamX = static_cast<double *>(p);
+  }
+  c->adj.n_io = (int32_t)nio;
+  // the Windkessel outlets' state per checkpoint slot
+  if (c->n_wk > 0 && c->adj_wk_nslots < (int64_t)n_snap + 1) {
+    if (c->adj_wk_slots) {
+      (void)hipFree(c->adj_wk_slots);
+      c->dev_bytes -= c->adj_wk_nslots * (int64_t)(nio * (sizeof(WkParams) + 2 * sizeof(double)));
+      c->adj_wk_slots = nullptr;
+      c->adj_wk_nslots = 0;
+    }
+    if (hlb_status st = dev_alloc(c, &p, (size_t)(n_snap + 1) * nio * (sizeof(WkParams) + 2 * sizeof(double))))
+      return st;
+    c->adj_wk_slots = p;
+    c->adj_wk_nslots = (int64_t)n_snap + 1;
   }
   if (c->adj_dA_len < std::max<int64_t>(1, nio * n)) {
     if (c->adj.dA) {
@@ -1871,6 +1912,7 @@ hlb_status adjoint_sweep(hlb_ctx *c, int64_t n, int64_t obj_t0, int64_t obj_t1, 
   HIP_TRY(launch_zero(c->adj.dphi, np, c->stream));
   HIP_TRY(launch_zero(c->adj.J + 8, kAdjJSlots, c->stream));
   HIP_TRY(launch_zero(c->adj.dA, std::max<int64_t>(1, nio * n), c->stream));
+  HIP_TRY(launch_zero(c->adj.lamX, std::max<int64_t>(1, nio), c->stream));
   Revolve R;
   R.c = c;
   R.t0 = t_start;
@@ -1893,6 +1935,7 @@ hlb_status adjoint_sweep(hlb_ctx *c, int64_t n, int64_t obj_t0, int64_t obj_t1, 
     if (e == hipSuccess)
       e = hipMemcpyAsync(c->d.acc, c->adj.J + 1, 4 * sizeof(double), hipMemcpyDeviceToDevice, c->stream);
     if (e != hipSuccess) st = fail(HLB_EDEVICE, "restoring the state: %s", hipGetErrorString(e));
+    if (!st) st = R.wk_state(0, false);
   }
   c->cur = cur0;
   c->direct = direct0;

@@ -79,8 +79,13 @@ def test_windkessel_fp32_and_errors():
     with pytest.raises(hlb.HLBError, match="not a Windkessel"):
         hlb.hlb_windkessel_state(sim.ctx, k_out)
     sim.close()
+    # the adjoint carries the model (parity: tests/test_gpu_adjoint_windkessel.py)
+    # and leaves the model's state as it found it
     adj = hlb.Simulation.create(g, tau, tables=tables, adjoint=True)
     hlb.hlb_set_windkessel(adj.ctx, k_out, (1.0, 0.001, 0.0, 0.001, 0.0))
-    with pytest.raises(hlb.HLBError, match="Windkessel"):
-        hlb.hlb_adjoint_run(adj.ctx, 10, 0, 10, 2)
+    adj.step(5)
+    before = hlb.hlb_windkessel_state(adj.ctx, k_out)
+    J, dA, dphi, fw = hlb.hlb_adjoint_run(adj.ctx, 10, 5, 15, 2)
+    assert np.isfinite(J) and J > 0 and np.all(np.isfinite(dA))
+    assert hlb.hlb_windkessel_state(adj.ctx, k_out) == before
     adj.close()
