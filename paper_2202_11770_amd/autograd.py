@@ -18,7 +18,10 @@ the parameters, the objective and the gradients never leave the GPU.
 
 ``IoletFluxObjective`` does the same for the weighted net outflow through
 the iolets, with gradients also for the per-step ghost densities of the
-pressure iolets.
+pressure iolets.  Windkessel outlets set on the simulation
+(hlb_set_windkessel) stay on, and the adjoint runs through their model,
+as long as no ghost-density table is passed (R None): a table passed for a
+pressure iolet replaces its model.
 
 ``fourier_inlet(theta, n, period, base)`` builds A(s) = base + sum_k
 a_k cos(2 pi k s / period) + b_k sin(2 pi k s / period) from theta = (a, b)
