@@ -272,6 +272,25 @@ __device__ inline void bulk_offsets(const GatherArgs &a, int64_t p, int64_t blk,
   off[17] = r[4].y;
 }
 
+// bulk_offsets from the rows of p's block staged in LDS: lrows holds the
+// rows of segments seg_base[blk] .. seg_base[blk] + k_max of the block, so
+// the row of p is entry seg_delta[p].
+__device__ inline void lds_offsets(const GatherArgs &a, int64_t p, const int4 *lrows, int32_t (&off)[Q - 1]) {
+  const int4 *row = lrows + (kSegRow / 4) * (int32_t)ld_stream(a.seg_delta + p);
+  int4 r[5];
+#pragma unroll
+  for (int k = 0; k < 5; ++k) r[k] = row[k];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    off[4 * k] = r[k].x;
+    off[4 * k + 1] = r[k].y;
+    off[4 * k + 2] = r[k].z;
+    off[4 * k + 3] = r[k].w;
+  }
+  off[16] = r[4].x;
+  off[17] = r[4].y;
+}
+
 // bulk_offsets for a whole wavefront (all 64 lanes active or not, each with
 // its own p in ascending order): where the lanes' segments are at most two
 // consecutive ones, both rows are read with scalar loads, which bypass the
@@ -325,9 +344,11 @@ __device__ inline void bulk_offsets_wave(const GatherArgs &a, int64_t p, int64_t
 // IOLET = false: the site has only fluid and wall links.
 // blk: the kSegBlock-position block of p (bulk+wall group only).
 // NARROW: see at().
-template <bool IOLET, bool POROUS, bool SH, bool NARROW = false, typename T, typename C>
+// LROWS (bulk+wall group): the block's segment rows are staged in LDS at
+// lrows (see lds_offsets).
+template <bool IOLET, bool POROUS, bool SH, bool NARROW = false, bool LROWS = false, typename T, typename C>
 __device__ inline C gather(const T *__restrict__ A, int64_t p, int64_t blk, const GatherArgs &a, C (&g)[Q],
-                           WkFlux *wkf = nullptr) {
+                           WkFlux *wkf = nullptr, const int4 *lrows = nullptr) {
   const int64_t np = a.np;
   C flux = 0;
   if constexpr (!IOLET && NARROW) {
@@ -338,7 +359,9 @@ __device__ inline C gather(const T *__restrict__ A, int64_t p, int64_t blk, cons
     // FP16 is bound by the vector path's address processing: there the
     // scalar row loads took the step kernel from 0.335 to 0.330 ms on a
     // 2e7-site tree; FP64, bound by HBM, measured 0.2% slower with them.
-    if constexpr (sizeof(T) == 2)
+    if constexpr (LROWS)
+      lds_offsets(a, p, lrows, off);
+    else if constexpr (sizeof(T) == 2)
       bulk_offsets_wave(a, p, blk, off);
     else
       bulk_offsets(a, p, blk, off);
@@ -371,7 +394,10 @@ __device__ inline C gather(const T *__restrict__ A, int64_t p, int64_t blk, cons
     // Bulk+wall group: every link, bounce-back included, is one load; the
     // offsets are fetched before the 18 gathers are issued.
     int32_t off[Q - 1];
-    bulk_offsets(a, p, blk, off);
+    if constexpr (LROWS)
+      lds_offsets(a, p, lrows, off);
+    else
+      bulk_offsets(a, p, blk, off);
     const int32_t p32 = (int32_t)p;
     g[0] = ld(at<NARROW>(A, p32, 0));
 #pragma unroll

@@ -52,6 +52,14 @@ constexpr int kStepWaves =
     SPT == 2 ? 4 : (std::is_same<T, double>::value ? 4 : (std::is_same<T, float>::value ? 5 : 6));
 template <typename T>
 constexpr bool kStepNarrow = !std::is_same<T, float>::value;
+// Whether the bulk path stages each block's segment rows through LDS: one
+// coalesced pass over the block's rows (typically 20-50 of them) replaces
+// every lane's five 16-byte row loads, each of which touches a cache line
+// per distinct segment of its wavefront.  FP64 and FP32: +0.4% on the 2e7-
+// and +0.5-1.0% on the 2e8-site tree.  FP16 keeps its wavefront-wide scalar
+// row loads: the staging pass and barrier cost it 2-5%.
+template <typename T>
+constexpr bool kStepLdsRows = sizeof(T) != 2;
 
 // SPT: bulk+wall sites per thread.  With SPT = 2 a workgroup takes two
 // consecutive 256-position blocks and each thread one position of each (both
@@ -82,9 +90,20 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kStepWav
   } else if constexpr (SPT == 1) {
     const int64_t blk = blk0 + block_id(b - nb_io, nb_bulk, xcd_chunk);
     const int64_t p = blk * kBlock + threadIdx.x;
+    constexpr bool LROWS = kStepLdsRows<T>;
+    // rows of the block's segments: seg_base[blk] .. + seg_delta of its last
+    // position (at most kSegBlock rows)
+    __shared__ int4 lrows[LROWS ? kSegBlock * (kSegRow / 4) : 1];
+    if constexpr (LROWS) {
+      const int64_t last = blk * kBlock + kBlock - 1 < n0 ? blk * kBlock + kBlock - 1 : n0 - 1;
+      const int32_t n4 = ((int32_t)a.seg_delta[last] + 1) * (kSegRow / 4);
+      const int4 *rows = reinterpret_cast<const int4 *>(a.seg_off + (int64_t)a.seg_base[blk] * kSegRow);
+      for (int k = threadIdx.x; k < n4; k += kBlock) lrows[k] = rows[k];
+      __syncthreads();
+    }
     if (p < n0) {
       C g[Q];
-      flux = gather<false, POROUS, SH, NARROW>(A, p, blk, a, g);
+      flux = gather<false, POROUS, SH, NARROW, LROWS>(A, p, blk, a, g, nullptr, lrows);
       collide<SH>(g, omega, C(a.rho0));
       if constexpr (NARROW) {
         using N = Narrow<T>;
