@@ -272,11 +272,10 @@ __device__ inline void bulk_offsets(const GatherArgs &a, int64_t p, int64_t blk,
   off[17] = r[4].y;
 }
 
-// bulk_offsets from the rows of p's block staged in LDS: lrows holds the
-// rows of segments seg_base[blk] .. seg_base[blk] + k_max of the block, so
-// the row of p is entry seg_delta[p].
-__device__ inline void lds_offsets(const GatherArgs &a, int64_t p, const int4 *lrows, int32_t (&off)[Q - 1]) {
-  const int4 *row = lrows + (kSegRow / 4) * (int32_t)ld_stream(a.seg_delta + p);
+// bulk_offsets from p's row staged in LDS (the rows of p's block are the
+// segments seg_base[blk] .. seg_base[blk] + seg_delta of its last position;
+// p's row is entry seg_delta[p]).
+__device__ inline void lds_offsets(const int4 *row, int32_t (&off)[Q - 1]) {
   int4 r[5];
 #pragma unroll
   for (int k = 0; k < 5; ++k) r[k] = row[k];
@@ -344,11 +343,11 @@ __device__ inline void bulk_offsets_wave(const GatherArgs &a, int64_t p, int64_t
 // IOLET = false: the site has only fluid and wall links.
 // blk: the kSegBlock-position block of p (bulk+wall group only).
 // NARROW: see at().
-// LROWS (bulk+wall group): the block's segment rows are staged in LDS at
-// lrows (see lds_offsets).
+// LROWS (bulk+wall group): p's segment row is staged in LDS at lrow (see
+// lds_offsets).
 template <bool IOLET, bool POROUS, bool SH, bool NARROW = false, bool LROWS = false, typename T, typename C>
 __device__ inline C gather(const T *__restrict__ A, int64_t p, int64_t blk, const GatherArgs &a, C (&g)[Q],
-                           WkFlux *wkf = nullptr, const int4 *lrows = nullptr) {
+                           WkFlux *wkf = nullptr, const int4 *lrow = nullptr) {
   const int64_t np = a.np;
   C flux = 0;
   if constexpr (!IOLET && NARROW) {
@@ -360,7 +359,7 @@ __device__ inline C gather(const T *__restrict__ A, int64_t p, int64_t blk, cons
     // scalar row loads took the step kernel from 0.335 to 0.330 ms on a
     // 2e7-site tree; FP64, bound by HBM, measured 0.2% slower with them.
     if constexpr (LROWS)
-      lds_offsets(a, p, lrows, off);
+      lds_offsets(lrow, off);
     else if constexpr (sizeof(T) == 2)
       bulk_offsets_wave(a, p, blk, off);
     else
@@ -395,7 +394,7 @@ __device__ inline C gather(const T *__restrict__ A, int64_t p, int64_t blk, cons
     // offsets are fetched before the 18 gathers are issued.
     int32_t off[Q - 1];
     if constexpr (LROWS)
-      lds_offsets(a, p, lrows, off);
+      lds_offsets(lrow, off);
     else
       bulk_offsets(a, p, blk, off);
     const int32_t p32 = (int32_t)p;

@@ -56,8 +56,8 @@ constexpr bool kStepNarrow = !std::is_same<T, float>::value;
 // coalesced pass over the block's rows (typically 20-50 of them) replaces
 // every lane's five 16-byte row loads, each of which touches a cache line
 // per distinct segment of its wavefront.  FP64 and FP32: +0.4% on the 2e7-
-// and +0.5-1.0% on the 2e8-site tree.  FP16 keeps its wavefront-wide scalar
-// row loads: the staging pass and barrier cost it 2-5%.
+// and +0.5-1.3% on the 2e8-site tree.  FP16 keeps its wavefront-wide scalar
+// row loads: the staging pass and barrier cost it 3-5%.
 template <typename T>
 constexpr bool kStepLdsRows = sizeof(T) != 2;
 
@@ -94,7 +94,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kStepWav
     // rows of the block's segments: seg_base[blk] .. + seg_delta of its last
     // position (at most kSegBlock rows)
     __shared__ int4 lrows[LROWS ? kSegBlock * (kSegRow / 4) : 1];
+    int32_t k_row = 0;
     if constexpr (LROWS) {
+      // p's row in the block, loaded before the pass so that the two loads'
+      // latencies overlap (no load moves across the barrier)
+      k_row = p < n0 ? (int32_t)ld_stream(a.seg_delta + p) : 0;
       const int64_t last = blk * kBlock + kBlock - 1 < n0 ? blk * kBlock + kBlock - 1 : n0 - 1;
       const int32_t n4 = ((int32_t)a.seg_delta[last] + 1) * (kSegRow / 4);
       const int4 *rows = reinterpret_cast<const int4 *>(a.seg_off + (int64_t)a.seg_base[blk] * kSegRow);
@@ -103,7 +107,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kStepWav
     }
     if (p < n0) {
       C g[Q];
-      flux = gather<false, POROUS, SH, NARROW, LROWS>(A, p, blk, a, g, nullptr, lrows);
+      flux = gather<false, POROUS, SH, NARROW, LROWS>(A, p, blk, a, g, nullptr, lrows + (kSegRow / 4) * k_row);
       collide<SH>(g, omega, C(a.rho0));
       if constexpr (NARROW) {
         using N = Narrow<T>;
