@@ -106,15 +106,22 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def stored_traffic(storage, n_sites):
+def order_tag(order, block):
+    """Site order as recorded with the counters: "bands7", "columns6", "lex", ..."""
+    return f"{order}{block}" if order in ("bands", "columns") else order
+
+
+def stored_traffic(storage, n_sites, order):
     """HBM bytes per step-kernel launch from the committed rocprofv3 counter
-    summary, if it was taken on the current kernel source and workload; else None."""
+    summary, if it was taken on the current kernel source, workload and site
+    order (an order_tag); else None."""
     p = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(p):
         return None
     sha = kernel_source_hash()
     for e in json.load(open(p)).get("entries", []):
-        if e.get("storage") == storage and e.get("n_sites") == n_sites and e.get("kernel_sha") == sha:
+        if (e.get("storage") == storage and e.get("n_sites") == n_sites and e.get("kernel_sha") == sha
+                and e.get("order") == order):
             return e.get("bytes_per_launch")
     return None
 
@@ -154,7 +161,9 @@ def run_storage(g, tables, tau, storage, steps, warmup, scheme="pull", windkesse
     # one step kernel updates every site of every group
     achieved = bpl * n / (st["kernel_ms"] * 1e-3) / 1e9
     order = {v: k for k, v in hlb.ORDER.items()}[info["order"]]
+    order_block = ORDER[1] or hlb.hlb_default_options().order_block
     return dict(storage=storage, n_sites=n, bytes_per_lup=bpl, ms_per_step=dt / steps * 1e3, order=order,
+                order_block=order_block if order in ("bands", "columns") else None,
                 xcd_remap=info["xcd_remap"],
                 mlups=mlups, alg_gbs=bpl * n * steps / dt / 1e9, kernel_ms=st["kernel_ms"],
                 event_step_ms=st["step_ms"], kernel_gbs=achieved,
@@ -546,7 +555,7 @@ def main():
     compare = None
     if args.compare_steps > 0:
         compare = compare_storages(g, tables, tau, args.storages.split(","), args.compare_steps)
-    traffic = stored_traffic(main_st, R["n_sites"])
+    traffic = stored_traffic(main_st, R["n_sites"], order_tag(R["order"], R["order_block"]))
     out = {
         "metric": "MLUPS & achieved HBM GB/s, FP64 vs FP32/FP16 storage at stated error",
         "value": round(R["mlups"], 2),
@@ -561,7 +570,8 @@ def main():
         "dtype": {"f64": "f64", "f32": "f32-storage", "f16": "f16-storage"}[main_st],
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {desc}; {g.n} fluid sites, tau {tau}, storage {main_st}",
-                   "n_sites": g.n, "storage": main_st, "order": R["order"], "xcd_remap": R["xcd_remap"],
+                   "n_sites": g.n, "storage": main_st, "order": R["order"], "order_block": R["order_block"],
+                   "xcd_remap": R["xcd_remap"],
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(R["kernel_gbs"], 1), "peak": PEAK_GBS, "unit": "GB/s",
                      "frac": round(R["frac"], 4), "traffic": traffic,

@@ -84,11 +84,13 @@ enum {
 /* Internal site order (all keep the six types grouped). */
 typedef enum {
   HLB_ORDER_INPUT = 0,  /* caller order within each group */
-  HLB_ORDER_LEX = 1,    /* lexicographic (z, y, x) (default) */
+  HLB_ORDER_LEX = 1,    /* lexicographic (z, y, x) */
   HLB_ORDER_MORTON = 2, /* Morton (Z-order) curve */
   HLB_ORDER_BRICK = 3,  /* Morton order of 4x4x4 bricks, lexicographic inside */
   HLB_ORDER_BANDS = 4,  /* bands of 2^order_block consecutive y rows, in y
-                           order; lexicographic (z, y, x) inside a band */
+                           order; lexicographic (z, y, x) inside a band
+                           (default, 128 rows: the same as lexicographic
+                           below 128 rows in y) */
   HLB_ORDER_COLUMNS = 5 /* columns of 2^order_block x 2^order_block in (x, y),
                            in (y, x) order; lexicographic (z, y, x) inside */
 } hlb_order;
@@ -118,7 +120,7 @@ typedef struct {
 
 typedef struct {
   int32_t storage;     /* hlb_storage (default HLB_F64) */
-  int32_t order;       /* hlb_order (default HLB_ORDER_LEX) */
+  int32_t order;       /* hlb_order (default HLB_ORDER_BANDS) */
   int32_t xcd_remap;   /* K > 0: renumber the bulk kernel's workgroups so that
                           each of the 8 XCDs gets K consecutive 256-position
                           blocks of every window of 8K blocks; 0: plain block
@@ -148,7 +150,7 @@ typedef struct {
                           the Windkessel outflow order-dependent). */
   int32_t order_block; /* log2 of the band / column width of
                           HLB_ORDER_BANDS and HLB_ORDER_COLUMNS, 1..16
-                          (default 6); ignored by the other orders */
+                          (default 7); ignored by the other orders */
   int32_t ladd_rho_local; /* density in the Ladd rule (Sec. 2.3.2):
                           0 (default) the reference density rho0;
                           1 the site's own density at the time of the

@@ -448,7 +448,7 @@ const char *hlb_last_error(void) { return g_err.c_str(); }
 hlb_status hlb_default_options(hlb_options *opt) {
   if (!opt) return fail(HLB_EINVAL, "null options");
   opt->storage = HLB_F64;
-  opt->order = HLB_ORDER_LEX;
+  opt->order = HLB_ORDER_BANDS;
   opt->xcd_remap = -1;
   opt->adjoint = 0;
   opt->rho0 = 1.0;
@@ -456,7 +456,7 @@ hlb_status hlb_default_options(hlb_options *opt) {
   opt->scheme = HLB_SCHEME_PULL;
   opt->sites_per_thread = 0;
   opt->graph_steps = 0;
-  opt->order_block = 6;
+  opt->order_block = 7;
   opt->ladd_rho_local = 0;
   return HLB_OK;
 }

@@ -35,8 +35,8 @@ def test_exports_every_declared_symbol():
 
 def test_default_options():
     o = hlb.hlb_default_options()
-    assert (o.storage, o.order, o.xcd_remap, o.adjoint, o.rho0, o.max_device_bytes) == (0, 1, -1, 0, 1.0, 0)
-    assert (o.scheme, o.sites_per_thread, o.graph_steps, o.order_block) == (hlb.HLB_SCHEME_PULL, 0, 0, 6)
+    assert (o.storage, o.order, o.xcd_remap, o.adjoint, o.rho0, o.max_device_bytes) == (0, hlb.ORDER["bands"], -1, 0, 1.0, 0)
+    assert (o.scheme, o.sites_per_thread, o.graph_steps, o.order_block) == (hlb.HLB_SCHEME_PULL, 0, 0, 7)
     assert o.ladd_rho_local == 0
 
 

@@ -23,8 +23,9 @@ def test_stored_traffic_matches_the_current_code():
     sha = bench.kernel_source_hash()
     assert all(e["kernel_sha"] == sha for e in entries), "profiles/traffic.json was taken on other kernel code"
     for e in entries:
-        assert bench.stored_traffic(e["storage"], e["n_sites"]) == e["bytes_per_launch"]
-    assert bench.stored_traffic("f64", 12345) is None
+        assert bench.stored_traffic(e["storage"], e["n_sites"], e["order"]) == e["bytes_per_launch"]
+        assert bench.stored_traffic(e["storage"], e["n_sites"], "morton") is None
+    assert bench.stored_traffic("f64", 12345, "bands7") is None
 
 
 def test_code_hash_ignores_comments(tmp_path, monkeypatch):
