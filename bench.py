@@ -242,6 +242,18 @@ def run_split(g, tables, tau, storage, steps, warmup, nparts, exchange="direct")
             "halo_values_per_step": n_halo, "ghost_sites": int(ghosts)}
 
 
+def run_split_fresh(workload_name, storage, steps, warmup, nparts, exchange):
+    """run_split in a process of its own.  The split's streams map onto the
+    GPU's few hardware queues in an order that depends on what the process
+    ran before: in one process a split run after another one measured up to
+    40% slower than the same run first, so every split run starts fresh."""
+    import subprocess
+    cmd = [sys.executable, os.path.abspath(__file__), "--workload", workload_name, "--steps", str(steps),
+           "--warmup", str(warmup), "--split-one", f"{storage},{exchange},{nparts}"]
+    out = subprocess.run(cmd, capture_output=True, text=True, check=True).stdout
+    return json.loads([l for l in out.splitlines() if l.startswith("{")][-1])
+
+
 def oracle_rate(g, tables, tau, budget_s):
     """Oracle MLUPS on a bounded sample: steps (after one untimed) until about
     budget_s of work.  Returns (mlups, steps)."""
@@ -452,6 +464,7 @@ def main():
                     help="also time the oracle (all threads and one) beside the GPU on four configurations")
     ap.add_argument("--windkessel", action="store_true",
                     help="also time the workload with every pressure outlet a three-element Windkessel")
+    ap.add_argument("--split-one", default=None, help=argparse.SUPPRESS)  # storage,exchange,parts (run_split_fresh)
     ap.add_argument("--split", type=int, default=0,
                     help="also time the workload as this many partitions with the halo exchange (one GPU)")
     ap.add_argument("--compare-steps", type=int, default=None,
@@ -468,6 +481,11 @@ def main():
     import torch
     torch.cuda.set_device(int(os.environ.get("LOCAL_RANK", "0")))
     tau, def_steps, def_storages, desc = WORKLOADS[args.workload]
+    if args.split_one:
+        st, ex, nparts = args.split_one.split(",")
+        g, tables = workload(args.workload)
+        print(json.dumps(run_split(g, tables, tau, st, args.steps or def_steps, args.warmup, int(nparts), exchange=ex)))
+        return
     args.steps = args.steps or def_steps
     args.storages = args.storages or def_storages
     global ORDER
@@ -548,7 +566,7 @@ def main():
         for st in args.storages.split(","):
             split[st] = {}
             for ex in ("direct", "copy"):
-                r = run_split(g, tables, tau, st, args.steps, args.warmup, args.split, exchange=ex)
+                r = run_split_fresh(args.workload, st, args.steps, args.warmup, args.split, ex)
                 r["overhead_vs_single"] = round(results[st]["mlups"] / r["mlups"] - 1.0, 4)
                 split[st][ex] = r
                 log(f"split {st}: {r}")

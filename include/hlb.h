@@ -421,6 +421,22 @@ hlb_status hlb_halo_clear_peers(hlb_ctx *ctx);
 hlb_status hlb_step_edge(hlb_ctx *ctx);
 hlb_status hlb_step_mid(hlb_ctx *ctx);
 
+/* Run hlb_step_mid on a second caller-owned HIP stream (hipStream_t), so
+ * that the mid-domain update of step t overlaps the edge update and the
+ * exchange of the same step (Sec. 3.1: the edge sites are updated and sent
+ * while the mid-domain sites are updated); NULL (the default) runs it on
+ * the context's stream.  The library then orders nothing between the two
+ * streams; the caller must make
+ *   the context's stream wait for the previous hlb_step_mid before each
+ *     hlb_step_edge (the mid step writes the sites the edge step reads and
+ *     reads the buffer the edge step writes), and before any other call on
+ *     the context;
+ *   this stream wait for the previous hlb_step_edge (and for the work that
+ *     set up the state) before each hlb_step_mid.
+ * The stream must outlive its use.  Errors: HLB_ESTATE (between
+ * hlb_step_edge and hlb_step_mid). */
+hlb_status hlb_set_mid_stream(hlb_ctx *ctx, void *hip_stream);
+
 /* Objective of hlb_adjoint_run (not a rule of the paper).
  *   HLB_OBJ_WSS (default): the wall shear stress (hlb_macros' definition)
  *     of the state at t, summed over the sites with wall links;

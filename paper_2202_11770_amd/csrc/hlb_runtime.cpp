@@ -171,6 +171,7 @@ struct hlb_ctx {
   int device = 0;
   hipStream_t own_stream = nullptr;
   hipStream_t stream = nullptr;
+  hipStream_t mid_stream = nullptr;  // hlb_step_mid's stream (null: stream)
   int cur = 0;          // buffer holding the post-collision state of time t
   bool direct = true;   // other buffer holds the pre-collision state of t
   // partition (hlb_create_part): per-site role and caller id -> position
@@ -865,6 +866,13 @@ hlb_status hlb_set_stream(hlb_ctx *c, void *s) {
   return HLB_OK;
 }
 
+hlb_status hlb_set_mid_stream(hlb_ctx *c, void *s) {
+  if (hlb_status st = check_ctx(c)) return st;
+  if (c->split_pending) return fail(HLB_ESTATE, "hlb_step_mid is pending");
+  c->mid_stream = static_cast<hipStream_t>(s);
+  return HLB_OK;
+}
+
 hlb_status hlb_set_iolet_table(hlb_ctx *c, int32_t k, const double *v, int64_t len) {
   if (hlb_status st = check_ctx(c)) return st;
   if (k < 0 || k >= (int32_t)c->iolets.size()) return fail(HLB_EINVAL, "iolet %d out of range", k);
@@ -1221,7 +1229,8 @@ hlb_status hlb_step_mid(hlb_ctx *c) {
   if (hlb_status st = check_ctx(c)) return st;
   if (!c->split_pending) return fail(HLB_ESTATE, "hlb_step_edge must come first");
   if (hlb_status st = bind(c)) return st;
-  HIP_TRY(launch_step(c->cfg, c->L, c->d, c->cur, c->t, c->stream, nullptr, nullptr, 2));
+  HIP_TRY(launch_step(c->cfg, c->L, c->d, c->cur, c->t, c->mid_stream ? c->mid_stream : c->stream, nullptr, nullptr,
+                      2));
   c->split_pending = false;
   c->cur = 1 - c->cur;
   c->direct = false;

@@ -13,7 +13,11 @@ receiver agree without negotiation.
 ``SplitSimulation`` runs one context per part on one GPU, each on its own
 stream.  Per step every part updates its edge sites (``hlb_step_edge``) and
 then its mid-domain sites (``hlb_step_mid``), which overlap the exchange.
-Two exchanges are built:
+With the direct exchange the mid step runs on a second stream of its part
+(``hlb_set_mid_stream``), so that it also overlaps the part's edge step: a
+part's edge step waits for its previous mid step (which wrote sites the
+edge step reads, and read the buffer it writes), and its mid step for its
+previous edge step.  Two exchanges are built:
 
 * ``exchange="direct"`` (default): the edge step writes each exchanged
   value straight into the ghost slot of the peer's population buffer that
@@ -108,6 +112,23 @@ def partition(geom, nparts: int = 2):
 
 _DTYPE = {"f64": "float64", "f32": "float32", "f16": "float16"}
 
+# Per part index, the part's two streams (its update stream, and the mid step's
+# stream of the direct exchange or the transfer stream of the copy exchange),
+# shared by every SplitSimulation of the process.  The GPU maps streams onto
+# a few hardware queues, and two streams that share one serialise: with new
+# streams per simulation the second simulation of a process measured up to
+# 40% slower than the first.  With these streams a repeated run of one
+# exchange runs as the first; a copy-exchange run after a direct-exchange
+# run of the same process still measured 33% slower (its transfer stream
+# was the mid stream before), so measurements start a process per run.
+_STREAMS = []
+
+
+def _part_streams(torch, r):
+    while len(_STREAMS) <= r:
+        _STREAMS.append((torch.cuda.Stream(), torch.cuda.Stream()))
+    return _STREAMS[r]
+
 
 class SplitSimulation:
     """One context per part on one GPU; see the module docstring."""
@@ -129,7 +150,7 @@ class SplitSimulation:
         opt = hlb.hlb_default_options()
         opt.storage = hlb.STORAGE[storage]
         opt.xcd_remap = int(xcd_remap)
-        self.ctx, self.s, self.c, self.send, self.recv = [], [], [], [], []
+        self.ctx, self.s, self.m, self.c, self.send, self.recv = [], [], [], [], [], []
         common = torch.cuda.Stream() if shared_stream else None
         self.send_slice, self.recv_slice = [], []
         for P in self.parts:
@@ -161,11 +182,18 @@ class SplitSimulation:
                 sl[q] = slice(off, off + P.recv[q][0].size)
                 off += P.recv[q][0].size
             self.recv_slice.append(sl)
-            s = common if common is not None else torch.cuda.Stream()
+            s, x = _part_streams(torch, len(self.ctx))
+            if common is not None:
+                s = common
             hlb.hlb_set_stream(ctx, s.cuda_stream)
+            m = None
+            if common is None and self.direct:
+                m = x
+                hlb.hlb_set_mid_stream(ctx, m.cuda_stream)
             self.ctx.append(ctx)
             self.s.append(s)
-            self.c.append(torch.cuda.Stream())
+            self.m.append(m)
+            self.c.append(None if self.direct else x)
             self.send.append(sb)
             self.recv.append(rb)
         self.unpacked = [None] * len(self.parts)
@@ -181,6 +209,7 @@ class SplitSimulation:
                     elem, bufs = hlb.hlb_halo_ghost_slots(self.ctx[q], rs, rd)
                     hlb.hlb_halo_add_peer(self.ctx[r], sites, dirs, bufs[0], bufs[1], elem)
         self.edge_done = [None] * len(self.parts)
+        self.mid_done = [None] * len(self.parts)  # each part's last mid step (mid stream)
         self.exchange()
 
     def _transfer(self, packed):
@@ -211,10 +240,17 @@ class SplitSimulation:
             e.record(self.s[r])
             self.unpacked[r] = e
 
+    def _join(self):
+        """Order later work on each part's stream after its mid steps."""
+        for s, m in zip(self.s, self.m):
+            if m is not None:
+                s.wait_stream(m)
+
     def exchange(self):
         """Fill every ghost from its owner's current state (after creation,
         init or set_state)."""
         torch = self.torch
+        self._join()
         if self.direct:
             torch.cuda.synchronize()  # every part's state is settled before any peer writes its ghosts
             for r, ctx in enumerate(self.ctx):
@@ -245,8 +281,19 @@ class SplitSimulation:
         torch = self.torch
         if self.direct:
             for _ in range(n):
-                done = []
+                done, before = [], []
                 for r, ctx in enumerate(self.ctx):
+                    m = self.m[r]
+                    if m is not None:
+                        if self.mid_done[r] is not None:
+                            self.s[r].wait_event(self.mid_done[r])
+                        # everything on the part's stream so far (its previous
+                        # edge step and exchange, any set-up), not this edge step
+                        e = torch.cuda.Event()
+                        e.record(self.s[r])
+                        before.append(e)
+                    else:
+                        before.append(None)
                     # the peers' previous edge steps wrote the ghosts this one
                     # reads and were the last to read the ghosts it writes
                     for q in self.nb[r]:
@@ -255,8 +302,15 @@ class SplitSimulation:
                     e = torch.cuda.Event()
                     e.record(self.s[r])
                     done.append(e)
-                for ctx in self.ctx:
+                for r, ctx in enumerate(self.ctx):
+                    m = self.m[r]
+                    if m is not None:
+                        m.wait_event(before[r])
                     hlb.hlb_step_mid(ctx)
+                    if m is not None:
+                        e = torch.cuda.Event()
+                        e.record(m)
+                        self.mid_done[r] = e
                 self.edge_done = done
             return
         for _ in range(n):
@@ -275,6 +329,7 @@ class SplitSimulation:
         self.torch.cuda.synchronize()
 
     def macros(self):
+        self._join()
         rho = np.empty(self.n)
         u = np.empty((self.n, 3))
         wss = np.empty(self.n)
@@ -285,6 +340,7 @@ class SplitSimulation:
         return rho, u, wss
 
     def mass(self) -> float:
+        self._join()
         return float(sum(hlb.hlb_mass_balance(ctx)[0] for ctx in self.ctx))
 
     def close(self):

@@ -120,6 +120,7 @@ _SIGS = {
     "hlb_halo_unpack": [_P],
     "hlb_step_edge": [_P],
     "hlb_step_mid": [_P],
+    "hlb_set_mid_stream": [_P, _P],
     "hlb_adjoint_run": [_P, _i64, _i64, _i64, _i32, _P, _P, _P, ctypes.POINTER(_i64)],
     "hlb_adjoint_run_device": [_P, _i64, _i64, _i64, _i32, _P, _P, _P, ctypes.POINTER(_i64)],
     "hlb_revolve_forward_steps": [_i64, _i32, ctypes.POINTER(_i64)],
@@ -303,6 +304,11 @@ def hlb_step_edge(ctx):
 
 def hlb_step_mid(ctx):
     _check(load().hlb_step_mid(ctx), "hlb_step_mid")
+
+
+def hlb_set_mid_stream(ctx, stream):
+    """stream: a hipStream_t as an int, or None (hlb_step_mid on the context's stream)."""
+    _check(load().hlb_set_mid_stream(ctx, _P(int(stream)) if stream else None), "hlb_set_mid_stream")
 
 
 def hlb_destroy(ctx):

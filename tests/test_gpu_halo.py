@@ -76,6 +76,8 @@ def test_split_porous_and_errors():
     P = sp.parts[0]
     assert hlb.hlb_info(ctx)["group_sites"][5] == P.glob.size - P.n_owned
     hlb.hlb_step_edge(ctx)
+    with pytest.raises(hlb.HLBError, match="pending"):
+        hlb.hlb_set_mid_stream(ctx, None)
     with pytest.raises(hlb.HLBError, match="split step"):
         hlb.hlb_step(ctx, 1)
     with pytest.raises(hlb.HLBError, match="split step"):
