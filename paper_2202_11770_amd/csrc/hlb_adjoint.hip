@@ -27,6 +27,7 @@ struct AdjArgs {
   double *mu;               // mu_t in, mu_{t-1} out (tiled)
   double *nu;               // nu_t (tiled)
   const int32_t *order;     // caller id per position (-1: padding)
+  int64_t n0;               // sites of the bulk+wall group
   double omega, tau;
   int in_window;            // t lies in the objective window
   int64_t n_steps;          // row length of dA
@@ -99,6 +100,32 @@ __device__ inline void link_masks(const GatherArgs &a, int64_t p, uint32_t &wall
   }
 }
 
+// The segment rows of a bulk+wall block staged in LDS, as in the forward
+// step kernel (one coalesced pass instead of five row loads per lane, and
+// per link-mask / gather pass): every thread of the block must call it.
+// Returns p's row.
+__device__ inline const int4 *stage_rows(const AdjArgs &A, int64_t blk, int64_t p, int4 *lrows) {
+  const GatherArgs &a = A.a;
+  const int32_t k_row = p < A.n0 ? (int32_t)ld_stream(a.seg_delta + p) : 0;
+  const int64_t last = blk * kBlock + kBlock - 1 < A.n0 ? blk * kBlock + kBlock - 1 : A.n0 - 1;
+  const int32_t n4 = ((int32_t)a.seg_delta[last] + 1) * (kSegRow / 4);
+  const int4 *rows = reinterpret_cast<const int4 *>(a.seg_off + (int64_t)a.seg_base[blk] * kSegRow);
+  for (int k = threadIdx.x; k < n4; k += kBlock) lrows[k] = rows[k];
+  __syncthreads();
+  return lrows + (kSegRow / 4) * k_row;
+}
+
+// link_masks of a bulk+wall position from its staged row.
+__device__ inline uint32_t wall_mask(const GatherArgs &a, int64_t p, const int4 *lrow) {
+  int32_t off[Q - 1];
+  lds_offsets(lrow, off);
+  uint32_t wall = 0;
+#pragma unroll
+  for (int i = 1; i < Q; ++i)
+    if ((uint32_t)((int32_t)p + off[i - 1]) >= (uint32_t)a.np) wall |= 1u << (i - 1);
+  return wall;
+}
+
 // nu_t = (dC/dg)^T mu_t + dWSS/dg_t for every site (the parameter terms
 // follow in k_adj_boundary, at the sites that have them).  The gathered
 // state g lives only until its moments are known.  mu is read once and nu
@@ -130,6 +157,10 @@ template <bool POROUS, bool WSS>
 __global__ __launch_bounds__(kBlock) void k_adj_collide(AdjArgs A) {
   const GatherArgs &a = A.a;
   const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  // bulk+wall blocks (block-uniform): the segment rows through LDS
+  __shared__ int4 lrows[kSegBlock * (kSegRow / 4)];
+  const bool bulk = (int64_t)blockIdx.x * kBlock < A.n0;
+  const int4 *lrow = bulk ? stage_rows(A, blockIdx.x, p, lrows) : nullptr;
   double jsum = 0.0;
   if (p < a.np && A.order[p] >= 0) {
     const int32_t p32 = (int32_t)p;
@@ -139,14 +170,18 @@ __global__ __launch_bounds__(kBlock) void k_adj_collide(AdjArgs A) {
     double pxx = 0, pyy = 0, pzz = 0, pxy = 0, pxz = 0, pyz = 0;  // second moments of g
     uint32_t wall = 0;
     if constexpr (!POROUS || WSS) {
-      uint32_t iol;
-      link_masks(a, p, wall, iol);
+      if (bulk) {
+        wall = wall_mask(a, p, lrow);
+      } else {
+        uint32_t iol;
+        link_masks(a, p, wall, iol);
+      }
     }
     constexpr bool kMuEarly = !POROUS && !WSS;
     {
       double g[Q];
-      if (p < a.io_begin)
-        gather<false, POROUS, false>(A.S, p, p / kBlock, a, g);
+      if (bulk)
+        gather<false, POROUS, false, false, true>(A.S, p, p / kBlock, a, g, nullptr, lrow);
       else
         gather<true, POROUS, false>(A.S, p, 0, a, g);
       if constexpr (kMuEarly) {
@@ -350,20 +385,24 @@ template <bool POROUS>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_adj_stream(AdjArgs A) {
   const GatherArgs &a = A.a;
   const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  // bulk+wall blocks (block-uniform): the segment rows through LDS
+  __shared__ int4 lrows[kSegBlock * (kSegRow / 4)];
+  const bool bulk = (int64_t)blockIdx.x * kBlock < A.n0;
+  const int4 *lrow = bulk ? stage_rows(A, blockIdx.x, p, lrows) : nullptr;
   if (p >= a.np || A.order[p] < 0) return;
   const int32_t p32 = (int32_t)p;
   const double ph = POROUS ? a.phi[p] : 0.0;
   // outflow weights w_k = dJ/dQ_k(t-1): a population leaving through a
   // pressure iolet adds w_k to its own adjoint (the fill does not depend on
   // it), and the fill's dependence on u enters with weight (nu - w_k)
-  if (p < a.io_begin) {
+  if (bulk) {
     // bulk+wall group (block-uniform): fluid and wall links only, one load
     // per link as in the forward gather
     // All 19 loads are issued before the first store: mu and nu are
     // different buffers, but the compiler cannot know it, and a store
     // between two loads would make each load wait for the one before.
     int32_t off[Q - 1];
-    bulk_offsets(a, p, p / kBlock, off);
+    lds_offsets(lrow, off);
     double v[Q];
     v[0] = A.nu[pidx(p32, 0)];
     uint32_t walls = 0;
@@ -488,6 +527,7 @@ hipError_t launch_adjoint_step(const LaunchCfg &cfg, const Layout &L, const DevP
   A.mu = b.mu;
   A.nu = b.nu;
   A.order = d.order;
+  A.n0 = L.gcnt[0];
   A.omega = 1.0 / cfg.tau;
   A.tau = cfg.tau;
   A.in_window = in_window;
