@@ -285,13 +285,16 @@ class SplitSimulation:
                 for r, ctx in enumerate(self.ctx):
                     m = self.m[r]
                     if m is not None:
-                        if self.mid_done[r] is not None:
-                            self.s[r].wait_event(self.mid_done[r])
                         # everything on the part's stream so far (its previous
-                        # edge step and exchange, any set-up), not this edge step
+                        # edge step and exchange, any set-up), recorded before
+                        # the wait on the previous mid step, so that the next
+                        # mid step does not wait for it a second time through
+                        # this stream
                         e = torch.cuda.Event()
                         e.record(self.s[r])
                         before.append(e)
+                        if self.mid_done[r] is not None:
+                            self.s[r].wait_event(self.mid_done[r])
                     else:
                         before.append(None)
                     # the peers' previous edge steps wrote the ghosts this one
