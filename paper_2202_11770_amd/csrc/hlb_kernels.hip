@@ -40,16 +40,17 @@ using namespace dev;
 // SIMD the step kernel is compiled for (the rare iolet blocks spill to fit,
 // the bulk path does not), and whether population addresses use 32-bit byte
 // offsets when a buffer allows it (see at()).  FP64: the natural 4 waves and
-// 32-bit offsets; FP32: the natural 5 waves and 64-bit addresses (32-bit
-// offsets measured 3% slower); FP16: 6 waves and 32-bit offsets.  Measured
-// again with the per-storage workgroup-to-XCD chunk on the 2e7- and 2e8-site
-// trees: FP64 4 waves (5, 6 slower by 0.5-1% on the 2e8 tree), FP32 5, FP16
-// 6 (8 waves 0.5-1.6% slower, 5 waves 2-3%).
+// 32-bit offsets; FP32: 6 waves and 64-bit addresses (32-bit offsets
+// measured 3% slower); FP16: 6 waves and 32-bit offsets.  Measured again
+// with the per-storage workgroup-to-XCD chunk on the 2e7- and 2e8-site
+// trees: FP64 4 waves (5, 6 slower by 0.5-1% on the 2e8 tree), FP16 6 (8
+// waves 0.5-1.6% slower, 5 waves 2-3%).  FP32, with the segment rows in LDS
+// and the banded order: 6 waves against its natural 5 gave +0.2-0.3% on the
+// trees and +0.9-1.0% on the 6e8-site forest; 4 waves cost 5%.
 // SPT = 2 (two bulk+wall sites per thread, see below) needs about twice the
 // registers of the bulk path: 4 waves.
 template <typename T, int SPT = 1, bool NARROW = true>
-constexpr int kStepWaves =
-    SPT == 2 ? 4 : (std::is_same<T, double>::value ? 4 : (std::is_same<T, float>::value ? 5 : 6));
+constexpr int kStepWaves = SPT == 2 ? 4 : (std::is_same<T, double>::value ? 4 : 6);
 template <typename T>
 constexpr bool kStepNarrow = !std::is_same<T, float>::value;
 // Whether the bulk path stages each block's segment rows through LDS: one
